@@ -1,0 +1,214 @@
+/*
+ * sph.h -- C ABI of libsph, an MI355X (gfx950) implementation of the smoothed
+ * particle hydrodynamics time step of Cavelan, Cabezon, Grabarczyk and Ciorba,
+ * "A Smoothed Particle Hydrodynamics Mini-App for Exascale" (arXiv 2005.02656).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers are DEVICE pointers unless a comment says (host).  Every array is
+ *   caller-owned, length cfg->n, stride 1, FP64 unless stated (structure of
+ *   arrays).  The library allocates nothing, frees nothing and keeps no global
+ *   state; all scratch lives in the caller's workspace `ws`.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *   only enqueues work on it and returns; results are ready when the stream is.
+ *   Two workspaces may be used concurrently on two streams.
+ * - Argument errors (NULL pointers, n <= 0, unknown enums, a periodic box that
+ *   is not larger than the smoothing kernel's reach) are returned synchronously
+ *   as SPH_E_ARG before anything is enqueued.  A failed HIP launch returns
+ *   SPH_E_HIP.  Conditions found on the device (list overflow, non-finite
+ *   values, singular IAD matrix, h beyond the minimum-image limit) set bits of
+ *   a sticky error word in `ws`; read and clear it with sph_status_sync.
+ *   Nothing aborts and nothing throws across this ABI.
+ * - Particle order: sph_build_cells permutes every state array in place into
+ *   the depth-first (Morton) order of section 4.3.  All later outputs are per
+ *   slot of that order; `id` carries each slot's original particle number.
+ *
+ * The stage entry points must be called in step order on one workspace:
+ *   build_cells -> update_h -> find_neighbors -> density -> iad ->
+ *   momentum_energy -> timestep -> integrate
+ * (sph_step does exactly that).  Each stage reads the arrays its comment names
+ * as inputs, so a caller may overwrite an input field between stages (the
+ * tests do, to feed identical inputs to an independent implementation).
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* sph_stream;  /* hipStream_t */
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_E_ARG = 1,               /* bad argument, detected on the host */
+    SPH_E_HIP = 2,               /* a HIP launch or query failed */
+    SPH_E_WORKSPACE = 3,         /* workspace NULL, misaligned or built for another n */
+    SPH_E_NEIGHBOR_OVERFLOW = 4, /* a neighbour count exceeded ng_max (lists truncated) */
+    SPH_E_CELL_RANGE = 5,        /* 4h >= box length on a periodic axis */
+    SPH_E_NONFINITE = 6,         /* NaN/Inf in density or rates */
+    SPH_E_SINGULAR_TAU = 7       /* det(tau) <= 0 in the IAD pass */
+} sph_status;
+
+/* bits of the device error word (sph_status_sync) */
+#define SPH_ERRBIT_NEIGHBOR_OVERFLOW (1u << 0)
+#define SPH_ERRBIT_CELL_RANGE (1u << 1)
+#define SPH_ERRBIT_NONFINITE (1u << 2)
+#define SPH_ERRBIT_SINGULAR_TAU (1u << 3)
+
+typedef enum { SPH_FP64 = 0, SPH_MIXED = 1 } sph_precision;
+typedef enum { SPH_EOS_IDEAL = 0, SPH_EOS_WEAKLY_COMPRESSIBLE = 1 } sph_eos;
+
+/* (host) Plain-old-data run configuration, read at every call. */
+typedef struct {
+    int64_t n;              /* number of particles, >= 1 */
+    double  box_lo[3];      /* box; used on periodic axes (open axes use the   */
+    double  box_hi[3];      /*   particles' bounding box, recomputed per call) */
+    int32_t periodic[3];    /* 1 = periodic axis, 0 = open */
+    int32_t eos;            /* sph_eos */
+    double  sinc_n;         /* exponent n of the sinc kernel S_n (eq. 6); integer 3..9 */
+    double  n_target;       /* target effective neighbour number of the h update */
+    int32_t ng_max;         /* neighbour-list capacity per particle, 1..4096 */
+    int32_t newton_iters;   /* Newton iterations per sph_update_h call, 0..64 */
+    double  h_ratio_max;    /* kappa: h stays in [h0/kappa, kappa*h0] per call, > 1 */
+    double  gamma;          /* ideal-gas adiabatic index (EOS_IDEAL) */
+    double  c0;             /* sound speed (EOS_WEAKLY_COMPRESSIBLE) */
+    double  alpha_av;       /* artificial-viscosity alpha (eq. 5) */
+    double  courant;        /* Courant criterion: courant * h/c */
+    double  dt_growth;      /* dt <= dt_growth * previous dt */
+    double  acc_dt;         /* acceleration criterion acc_dt * sqrt(h/|a|); 0 = off */
+    double  energy_dt;      /* energy criterion energy_dt * |u|/|du|; 0 = off */
+    int32_t precision;      /* sph_precision */
+    int32_t reserved;       /* must be 0 */
+} sph_config;
+
+/* Particle arrays (device, caller-owned).  State arrays are permuted in place by
+ * sph_build_cells; output arrays are written by the stage that names them. */
+typedef struct {
+    /* state: x^n, v^n (integer time), v^{n-1/2} (leapfrog half-step velocity) */
+    double  *x, *y, *z;
+    double  *vx, *vy, *vz;
+    double  *vhx, *vhy, *vhz;
+    double  *h;             /* smoothing length */
+    double  *m;             /* mass */
+    double  *u;             /* specific internal energy */
+    double  *du_m1;         /* du/dt of the previous step (Adams-Bashforth) */
+    double  *p_ref;         /* EOS_WEAKLY_COMPRESSIBLE only, else NULL */
+    double  *rho_ref;       /* EOS_WEAKLY_COMPRESSIBLE only, else NULL */
+    int64_t *id;            /* original particle number, permuted with the state */
+    /* outputs */
+    double  *rho, *omega, *p, *c;                 /* sph_density */
+    double  *c11, *c12, *c13, *c22, *c23, *c33;   /* sph_iad: C = tau^-1 */
+    double  *ax, *ay, *az, *du;                   /* sph_momentum_energy */
+} sph_particles;
+
+/* Global scalars (DEVICE memory, caller-owned, 14 doubles). */
+typedef struct {
+    double dt;       /* step being taken (written by sph_timestep) */
+    double dt_m1;    /* previous step, 0 before the first step */
+    double t;        /* simulated time */
+    double mass, mom[3], ang[3], e_kin, e_int;   /* conservation sums after the step */
+} sph_globals;
+
+/* (host) Bytes of workspace needed for cfg (pure function of n and ng_max).
+ * Returns 0 if cfg is invalid. */
+size_t sph_workspace_bytes(const sph_config* cfg);
+
+/* Clears the workspace header (error word, cached domain).  Call once after
+ * allocating ws; a zero-filled ws is already initialised. */
+sph_status sph_workspace_init(const sph_config* cfg, void* ws, sph_stream stream);
+
+/* Bounding box, largest h, 63-bit Morton keys, stable radix sort, permutation
+ * of every state array into key order, and the cell table (section 4.3: the
+ * particles are kept in the depth-first order of the octree; the domain size
+ * is the bounding box after particles moved).
+ * In: x y z h (and every other state array, permuted along).
+ * Out: state arrays permuted; ws holds keys, permutation and cell table. */
+sph_status sph_build_cells(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream);
+
+/* Smoothing-length update (section 4.1 "local spatial resolution"; the rule is
+ * not printed, the reading used is a fixed number `newton_iters` of Newton
+ * steps on the effective neighbour number (32 pi/3) B_n sum_b S_n(pi r/2h) =
+ * n_target, clamped to [h0/kappa, kappa h0]).
+ * In: x y z h (slot order of the last sph_build_cells).  Out: h in place. */
+sph_status sph_update_h(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream);
+
+/* Neighbour search within 2h (section 4.1, neighbours found with the tree of
+ * section 4.3, stored as integer lists as in section 4.3).
+ *   N(a)   = {b != a : r^2 < (2 h_a)^2}            gather set, nc[a] = |N(a)|
+ *   N_s(a) = {b != a : r^2 < (2 max(h_a,h_b))^2}   symmetric set, ns[a] = |N_s(a)|
+ * Lists are written to ws (sph_neighbors_view).  In: x y z h. */
+sph_status sph_find_neighbors(const sph_config* cfg, const sph_particles* p, void* ws,
+                              sph_stream stream);
+
+/* Density (eq. 1, self term included), grad-h term Omega (section 4.1) and the
+ * equation of state.  In: lists, x y z h m u (p_ref rho_ref).  Out: rho omega p c. */
+sph_status sph_density(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream);
+
+/* IAD matrix (section 4.1, integral approach to derivatives):
+ * tau_a = sum_{b in N(a)} (m_b/rho_b) W(r_ab,h_a) d_ab d_ab^T, C_a = tau_a^-1.
+ * det(tau) <= 0 writes C = 0 and sets SPH_ERRBIT_SINGULAR_TAU.
+ * In: lists, x y z h m rho.  Out: c11 c12 c13 c22 c23 c33. */
+sph_status sph_iad(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream);
+
+/* Momentum and energy rates with artificial viscosity (eqs. 2-5), summed over
+ * N_s(a), with A_ab(h_k) = C_k (x_b - x_a) W(r_ab, h_k), the AV acceleration
+ * subtracted and the energy prefactor P_a/(Omega_a rho_a^2).  Also reduces the
+ * per-particle time-step candidates (see sph_timestep) into ws.
+ * In: lists, x y z vx vy vz h m u rho omega p c c11..c33.  Out: ax ay az du. */
+sph_status sph_momentum_energy(const sph_config* cfg, sph_particles* p, void* ws,
+                               sph_stream stream);
+
+/* Global minimum time step (section 4.2, second global reduction; the rule is
+ * not printed, the reading used): g->dt = min over particles of
+ *   courant * (h/c),  acc_dt * sqrt(h/|a|),  energy_dt * (|u|/|du|)
+ * (zero coefficients switch the last two off), at most dt_growth * g->dt_m1 if
+ * g->dt_m1 > 0.
+ * In: the candidates of the last sph_momentum_energy.  Out: g->dt (device). */
+sph_status sph_timestep(const sph_config* cfg, sph_globals* g, void* ws, sph_stream stream);
+
+/* Integrator (section 4.1: second-order Press method for x and v, second-order
+ * Adams-Bashforth for u), read as kick-drift leapfrog with lambda = g->dt_m1:
+ * vh += a (lambda+dt)/2; x += vh dt (wrapped on periodic axes); v = vh + a dt/2;
+ * u += dt[(1+q) du - q du_m1], q = dt/(2 lambda) (Euler when lambda = 0);
+ * du_m1 = du.  Then the conservation sums (section 4.2, third reduction) into g
+ * and g->dt_m1 = g->dt, g->t += g->dt.
+ * In: state, ax ay az du, g->dt, g->dt_m1.  Out: state, g. */
+sph_status sph_integrate(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                         sph_stream stream);
+
+/* One full time step: build_cells, update_h, find_neighbors, density, iad,
+ * momentum_energy, timestep, integrate (the step order follows the three halo
+ * refreshes of section 4.4 and the global reductions of section 4.2). */
+sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                    sph_stream stream);
+
+/* (host) Views into ws after sph_find_neighbors: nc, ns (int32[n]) and the list
+ * (int32, column-major: entry j of slot a at list[j*stride + a]).  Slot a's
+ * gather neighbours are at j = 0..nc[a]-1; its symmetric-only neighbours
+ * (in N_s(a) but not N(a)) are at j = ng_max-(ns[a]-nc[a]) .. ng_max-1.
+ * Entries are slot indices.  Counts are true counts even when they exceed
+ * ng_max (then SPH_ERRBIT_NEIGHBOR_OVERFLOW is set and the lists truncated). */
+sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,
+                              const int32_t** ns, const int32_t** list, int64_t* stride);
+
+/* (host) Device pointers into ws after sph_build_cells: the sorted keys
+ * (uint64[n]) and the permutation perm (uint32[n], slot -> slot before the call). */
+sph_status sph_order_view(const sph_config* cfg, void* ws, const uint64_t** keys,
+                          const uint32_t** perm);
+
+/* Synchronises the stream, returns the most severe pending device condition
+ * (NONFINITE > SINGULAR_TAU > NEIGHBOR_OVERFLOW > CELL_RANGE) or SPH_OK, stores
+ * the raw bits in *bits (host, may be NULL) and clears the word. */
+sph_status sph_status_sync(void* ws, sph_stream stream, uint32_t* bits);
+
+/* (host) Static string naming a status. */
+const char* sph_status_string(sph_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H */

@@ -44,6 +44,8 @@ class Config:
     alpha_av: float = 1.0
     courant: float = 0.2
     dt_growth: float = 1.1
+    acc_dt: float = 0.2
+    energy_dt: float = 0.2
 
     def replace(self, **kw) -> "Config":
         return dataclasses.replace(self, **kw)
@@ -64,6 +66,8 @@ class _CConfig(C.Structure):
         ("alpha_av", C.c_double),
         ("courant", C.c_double),
         ("dt_growth", C.c_double),
+        ("acc_dt", C.c_double),
+        ("energy_dt", C.c_double),
     ]
 
 
@@ -82,6 +86,8 @@ def _cc(cfg: Config) -> _CConfig:
     c.alpha_av = cfg.alpha_av
     c.courant = cfg.courant
     c.dt_growth = cfg.dt_growth
+    c.acc_dt = cfg.acc_dt
+    c.energy_dt = cfg.energy_dt
     return c
 
 
@@ -102,7 +108,7 @@ def lib():
             getattr(_lib, f).restype = d
             getattr(_lib, f).argtypes = [d, d, d, d]
         _lib.ora_timestep.restype = d
-        _lib.ora_timestep.argtypes = [vp, i64, vp, vp, d]
+        _lib.ora_timestep.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, d]
     return _lib
 
 
@@ -232,9 +238,10 @@ def momentum_energy(cfg, x, y, z, vx, vy, vz, h, m, rho, omega, p, c, Cm, target
     return out
 
 
-def timestep(cfg, h, c, dt_m1):
-    h, c = _f64(h), _f64(c)
-    return lib().ora_timestep(C.byref(_cc(cfg)), C.c_int64(h.size), _p(h), _p(c), float(dt_m1))
+def timestep(cfg, h, c, u, ax, ay, az, du, dt_m1):
+    arrs = list(map(_f64, (h, c, u, ax, ay, az, du)))
+    return lib().ora_timestep(C.byref(_cc(cfg)), C.c_int64(arrs[0].size),
+                              *[_p(a) for a in arrs], float(dt_m1))
 
 
 STATE_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1")
@@ -308,7 +315,7 @@ def step(cfg, st, gl):
     Cm, sing = iad(cfg, x, y, z, h, st["m"], rho)
     me = momentum_energy(cfg, x, y, z, st["vx"], st["vy"], st["vz"], h, st["m"], rho, om, p,
                          c, Cm)
-    dt = timestep(cfg, h, c, gl["dt_m1"])
+    dt = timestep(cfg, h, c, st["u"], me["ax"], me["ay"], me["az"], me["du"], gl["dt_m1"])
     s0 = dict(st)
     s0["h"] = h
     new = integrate(cfg, s0, me["ax"], me["ay"], me["az"], me["du"], dt, gl["dt_m1"])
@@ -316,3 +323,8 @@ def step(cfg, st, gl):
     g = {"dt": dt, "dt_m1": dt, "t": gl["t"] + dt, **sm}
     fields = {"h": h, "rho": rho, "omega": om, "p": p, "c": c, "C": Cm, "singular": sing, **me}
     return new, g, fields
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().ora_num_threads())

@@ -41,6 +41,8 @@ typedef struct {
     double  gamma, c0;
     double  alpha_av;      /* alpha of the artificial viscosity (eq. 5) */
     double  courant, dt_growth;
+    double  acc_dt;        /* coefficient of the acceleration criterion, 0 = off */
+    double  energy_dt;     /* coefficient of the energy criterion, 0 = off */
 } ora_config;
 
 /* ------------------------------------------------------------------------ */
@@ -450,19 +452,37 @@ void ora_momentum_energy(const ora_config* cf, int64_t n, const double* x, const
 }
 
 /* ------------------------------------------------------------------------ */
-/* Global minimum time step (section 4.2, second global reduction; rule not */
-/* printed, reading): dt = courant * min_a h_a/c_a, limited to growth        */
-/* dt_growth * dt_m1 when a previous step exists.                            */
+/* Global minimum time step (section 4.2, second global reduction; the rule is */
+/* not printed, reading): the minimum over particles of                      */
+/*   courant * (h/c),  acc_dt * sqrt(h/|a|),  energy_dt * (|u|/|du|)          */
+/* (a zero coefficient switches a criterion off), limited to dt_growth times */
+/* the previous step when there is one.                                      */
 /* ------------------------------------------------------------------------ */
-double ora_timestep(const ora_config* cf, int64_t n, const double* h, const double* c,
-                    double dt_m1)
+double ora_dt_candidate(const ora_config* cf, double h, double c, double u, double ax,
+                        double ay, double az, double du)
 {
-    double mn = INFINITY;
-    for (int64_t a = 0; a < n; ++a) {
-        double q = h[a] / c[a];
-        if (q < mn) mn = q;
+    double q = cf->courant * (h / c);
+    if (cf->acc_dt > 0.0) {
+        double a = sqrt((ax * ax + ay * ay) + az * az);
+        double qa = cf->acc_dt * sqrt(h / a);
+        if (qa < q) q = qa;
     }
-    double dt = cf->courant * mn;
+    if (cf->energy_dt > 0.0) {
+        double qu = cf->energy_dt * (fabs(u) / fabs(du));
+        if (qu < q) q = qu;
+    }
+    return q;
+}
+
+double ora_timestep(const ora_config* cf, int64_t n, const double* h, const double* c,
+                    const double* u, const double* ax, const double* ay, const double* az,
+                    const double* du, double dt_m1)
+{
+    double dt = INFINITY;
+    for (int64_t a = 0; a < n; ++a) {
+        double q = ora_dt_candidate(cf, h[a], c[a], u[a], ax[a], ay[a], az[a], du[a]);
+        if (q < dt) dt = q;
+    }
     if (dt_m1 > 0.0) {
         double g = cf->dt_growth * dt_m1;
         if (g < dt) dt = g;
@@ -606,3 +626,11 @@ void ora_sort_keys(int64_t n, const uint64_t* keys, int64_t* perm)
     qsort(perm, (size_t)n, sizeof(int64_t), ora_key_cmp);
     g_sort_keys = NULL;
 }
+
+/* threads the OpenMP loops above run on */
+#ifdef _OPENMP
+#include <omp.h>
+int ora_num_threads(void) { return omp_get_max_threads(); }
+#else
+int ora_num_threads(void) { return 1; }
+#endif

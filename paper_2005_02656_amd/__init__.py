@@ -1,15 +1,9 @@
-"""MI355X-native SPH time step (arXiv 2005.02656): Python binding of libsph.
+"""MI355X-native SPH time step (arXiv 2005.02656).
 
-The compute path lives in the HIP library ``libsph.so`` (see ``include/sph.h``);
-this package only marshals arguments.  The library is loaded on first use and
-its absence raises: there is no CPU fallback.
+* ``paper_2005_02656_amd.sph``    -- ctypes binding of the HIP library libsph.so
+  (include/sph.h); it raises on first use if the library is not built: there is
+  no CPU fallback.
+* ``paper_2005_02656_amd.inputs`` -- seeded synthetic workloads (no method
+  arithmetic).
+* ``paper_2005_02656_amd.build``  -- compiles libsph.so for gfx950.
 """
-from . import inputs  # noqa: F401  (seeded workloads; no method arithmetic)
-
-
-def __getattr__(name):
-    # the binding is imported lazily so that ``inputs`` stays usable without a build
-    if name in ("sph", "lib"):
-        from . import sph as _sph
-        return _sph if name == "sph" else _sph.lib()
-    raise AttributeError(name)

@@ -1,0 +1,382 @@
+// sph_api.hip -- the C ABI of libsph: argument validation, workspace carve-up and
+// launch sequencing on the caller's stream.  No allocation, no global state.
+#include <math.h>
+#include <string.h>
+
+#include "sph_common.h"
+
+namespace sph {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(int64_t n, int ng_max)
+{
+    Layout L{};
+    L.n = n;
+    // largest level whose dense table has no more cells than particles
+    int lcap = 0;
+    while (lcap < kMaxLevel && (int64_t(1) << (3 * (lcap + 1))) <= (n > 1 ? n : 1)) ++lcap;
+    L.lcap = lcap;
+    L.ncells_cap = int64_t(1) << (3 * lcap);
+    L.nsort_blocks = (n + 4095) / 4096;
+    L.hist_len = 256 * L.nsort_blocks;
+    L.scan_blocks = (L.hist_len + 4095) / 4096;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.domain = take(sizeof(Domain));
+    L.sums = take(sizeof(double) * kSumBlocks * 10);
+    L.keys0 = take(sizeof(uint64_t) * n);
+    L.keys1 = take(sizeof(uint64_t) * n);
+    L.idx0 = take(sizeof(uint32_t) * n);
+    L.idx1 = take(sizeof(uint32_t) * n);
+    L.hist = take(sizeof(uint32_t) * L.hist_len);
+    L.scanpart = take(sizeof(uint32_t) * (L.scan_blocks + 1));
+    L.cstart = take(sizeof(int32_t) * L.ncells_cap);
+    L.cend = take(sizeof(int32_t) * L.ncells_cap);
+    L.chmax = take(sizeof(double) * L.ncells_cap);
+    L.nc = take(sizeof(int32_t) * n);
+    L.ns = take(sizeof(int32_t) * n);
+    size_t lst = sizeof(int32_t) * (size_t)ng_max * n;
+    size_t tmp = sizeof(double) * kMaxPermFields * n;
+    L.list = take(lst > tmp ? lst : tmp);
+    L.total = o;
+    return L;
+}
+
+Ws carve(void* ws, const Layout& L)
+{
+    char* b = (char*)ws;
+    Ws W;
+    W.dom = (Domain*)(b + L.domain);
+    W.sums = (double*)(b + L.sums);
+    W.keys0 = (uint64_t*)(b + L.keys0);
+    W.keys1 = (uint64_t*)(b + L.keys1);
+    W.idx0 = (uint32_t*)(b + L.idx0);
+    W.idx1 = (uint32_t*)(b + L.idx1);
+    W.hist = (uint32_t*)(b + L.hist);
+    W.scanpart = (uint32_t*)(b + L.scanpart);
+    W.cstart = (int32_t*)(b + L.cstart);
+    W.cend = (int32_t*)(b + L.cend);
+    W.chmax = (double*)(b + L.chmax);
+    W.nc = (int32_t*)(b + L.nc);
+    W.ns = (int32_t*)(b + L.ns);
+    W.list = (int32_t*)(b + L.list);
+    W.tmp = (double*)(b + L.list);
+    return W;
+}
+
+// B_n = 1 / (4 pi int_0^2 S_n(pi v/2) v^2 dv): composite Simpson on 2^13 and
+// 2^14 panels combined by one Richardson step (error O(h^6), far below 1e-16
+// relative), evaluated once per exponent when the library is loaded.
+static double simpson_bn(int n, int panels)
+{
+    const double hstep = 2.0 / panels;
+    double acc = 0.0;
+    for (int i = 0; i <= panels; ++i) {
+        double v = i * hstep;
+        double x = 0.5 * kPi * v;
+        double s = (i == 0) ? 1.0 : sin(x) / x;
+        double f = 1.0;
+        for (int k = 0; k < n; ++k) f *= s;
+        f *= v * v;
+        double w = (i == 0 || i == panels) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+        acc += w * f;
+    }
+    return acc * hstep / 3.0;
+}
+
+namespace {
+struct BnTable {
+    double v[10];
+    BnTable()
+    {
+        for (int n = 0; n < 10; ++n) {
+            if (n < 3) { v[n] = 0.0; continue; }
+            double coarse = simpson_bn(n, 1 << 13), fine = simpson_bn(n, 1 << 14);
+            double integral = fine + (fine - coarse) / 15.0;
+            v[n] = 1.0 / (4.0 * kPi * integral);
+        }
+    }
+};
+const BnTable kBn;  // constant after load
+}  // namespace
+
+double sinc_bn(int n) { return (n >= 3 && n <= 9) ? kBn.v[n] : 0.0; }
+
+Params make_params(const sph_config* cfg, double bn, int lcap)
+{
+    Params P{};
+    P.n = cfg->n;
+    P.stride = cfg->n;
+    for (int k = 0; k < 3; ++k) {
+        P.box_lo[k] = cfg->box_lo[k];
+        P.box_hi[k] = cfg->box_hi[k];
+        P.L[k] = cfg->box_hi[k] - cfg->box_lo[k];
+        P.halfL[k] = 0.5 * P.L[k];
+        P.periodic[k] = cfg->periodic[k] ? 1 : 0;
+    }
+    P.sinc_n = (int)cfg->sinc_n;
+    P.bn = bn;
+    P.n_target = cfg->n_target;
+    P.ng_max = cfg->ng_max;
+    P.newton_iters = cfg->newton_iters;
+    P.kappa = cfg->h_ratio_max;
+    P.eos = cfg->eos;
+    P.gamma = cfg->gamma;
+    P.c0 = cfg->c0;
+    P.alpha = cfg->alpha_av;
+    P.courant = cfg->courant;
+    P.growth = cfg->dt_growth;
+    P.acc_dt = cfg->acc_dt;
+    P.energy_dt = cfg->energy_dt;
+    P.lcap = lcap;
+    P.precision = cfg->precision;
+    return P;
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+namespace {
+
+bool config_ok(const sph_config* c)
+{
+    if (!c) return false;
+    if (c->n < 1 || c->n > (int64_t(1) << 31) - 1) return false;
+    if (c->ng_max < 1 || c->ng_max > 4096) return false;
+    if (c->newton_iters < 0 || c->newton_iters > 64) return false;
+    if (!(c->h_ratio_max > 1.0)) return false;
+    if (c->sinc_n != floor(c->sinc_n) || c->sinc_n < 3 || c->sinc_n > 9) return false;
+    if (c->eos != SPH_EOS_IDEAL && c->eos != SPH_EOS_WEAKLY_COMPRESSIBLE) return false;
+    if (c->precision != SPH_FP64 && c->precision != SPH_MIXED) return false;
+    if (c->reserved != 0) return false;
+    if (!(c->n_target > 0.0) || !(c->courant > 0.0) || !(c->dt_growth > 0.0)) return false;
+    if (!(c->alpha_av >= 0.0)) return false;
+    if (!(c->acc_dt >= 0.0) || !(c->energy_dt >= 0.0)) return false;
+    if (c->eos == SPH_EOS_IDEAL && !(c->gamma > 1.0)) return false;
+    if (c->eos == SPH_EOS_WEAKLY_COMPRESSIBLE && !(c->c0 > 0.0)) return false;
+    for (int k = 0; k < 3; ++k) {
+        if (c->periodic[k] != 0 && c->periodic[k] != 1) return false;
+        if (c->periodic[k] && !(c->box_hi[k] > c->box_lo[k])) return false;
+    }
+    return true;
+}
+
+bool state_ok(const sph_config* c, const sph_particles* p)
+{
+    if (!p) return false;
+    const void* req[] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->vhx, p->vhy, p->vhz,
+                         p->h, p->m, p->u, p->du_m1, p->id};
+    for (const void* q : req)
+        if (!q) return false;
+    if (c->eos == SPH_EOS_WEAKLY_COMPRESSIBLE && (!p->p_ref || !p->rho_ref)) return false;
+    return true;
+}
+
+struct Ctx {
+    Params P;
+    Layout L;
+    Ws W;
+    hipStream_t s;
+};
+
+sph_status prepare(const sph_config* cfg, void* ws, sph_stream stream, Ctx& c)
+{
+    if (!config_ok(cfg)) return SPH_E_ARG;
+    if (!ws || ((uintptr_t)ws & 255)) return SPH_E_WORKSPACE;
+    c.L = make_layout(cfg->n, cfg->ng_max);
+    c.W = carve(ws, c.L);
+    c.P = make_params(cfg, sinc_bn((int)cfg->sinc_n), c.L.lcap);
+    c.s = (hipStream_t)stream;
+    return SPH_OK;
+}
+
+sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_E_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+size_t sph_workspace_bytes(const sph_config* cfg)
+{
+    if (!config_ok(cfg)) return 0;
+    return make_layout(cfg->n, cfg->ng_max).total;
+}
+
+sph_status sph_workspace_init(const sph_config* cfg, void* ws, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    return hip_status(launch_clear_domain(c.W, c.s));
+}
+
+sph_status sph_build_cells(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!state_ok(cfg, p)) return SPH_E_ARG;
+    return hip_status(launch_build_cells(c.P, c.L, c.W, p, c.s));
+}
+
+sph_status sph_update_h(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!p || !p->x || !p->y || !p->z || !p->h) return SPH_E_ARG;
+    return hip_status(launch_update_h(c.P, c.L, c.W, p, c.s));
+}
+
+sph_status sph_find_neighbors(const sph_config* cfg, const sph_particles* p, void* ws,
+                              sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!p || !p->x || !p->y || !p->z || !p->h) return SPH_E_ARG;
+    return hip_status(launch_find_neighbors(c.P, c.L, c.W, p, c.s));
+}
+
+sph_status sph_density(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!p || !p->x || !p->y || !p->z || !p->h || !p->m || !p->u || !p->rho || !p->omega ||
+        !p->p || !p->c)
+        return SPH_E_ARG;
+    if (cfg->eos == SPH_EOS_WEAKLY_COMPRESSIBLE && (!p->p_ref || !p->rho_ref)) return SPH_E_ARG;
+    return hip_status(launch_density(c.P, c.L, c.W, p, c.s));
+}
+
+sph_status sph_iad(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!p || !p->x || !p->y || !p->z || !p->h || !p->m || !p->rho || !p->c11 || !p->c12 ||
+        !p->c13 || !p->c22 || !p->c23 || !p->c33)
+        return SPH_E_ARG;
+    return hip_status(launch_iad(c.P, c.L, c.W, p, c.s));
+}
+
+sph_status sph_momentum_energy(const sph_config* cfg, sph_particles* p, void* ws,
+                               sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!p || !p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->h || !p->m ||
+        !p->u || !p->rho || !p->omega || !p->p || !p->c || !p->c11 || !p->c12 || !p->c13 || !p->c22 ||
+        !p->c23 || !p->c33 || !p->ax || !p->ay || !p->az || !p->du)
+        return SPH_E_ARG;
+    return hip_status(launch_momentum_energy(c.P, c.L, c.W, p, c.s));
+}
+
+sph_status sph_timestep(const sph_config* cfg, sph_globals* g, void* ws, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!g) return SPH_E_ARG;
+    return hip_status(launch_timestep(c.P, c.W, g, c.s));
+}
+
+sph_status sph_integrate(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                         sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!g || !state_ok(cfg, p) || !p->ax || !p->ay || !p->az || !p->du) return SPH_E_ARG;
+    return hip_status(launch_integrate(c.P, c.W, p, g, c.s));
+}
+
+sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                    sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!g || !state_ok(cfg, p) || !p->rho || !p->omega || !p->p || !p->c || !p->c11 ||
+        !p->c12 || !p->c13 || !p->c22 || !p->c23 || !p->c33 || !p->ax || !p->ay || !p->az ||
+        !p->du)
+        return SPH_E_ARG;
+    hipError_t e;
+    if ((e = launch_build_cells(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    if ((e = launch_update_h(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    if ((e = launch_find_neighbors(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    if ((e = launch_density(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    if ((e = launch_iad(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    if ((e = launch_momentum_energy(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    if ((e = launch_timestep(c.P, c.W, g, c.s))) return SPH_E_HIP;
+    if ((e = launch_integrate(c.P, c.W, p, g, c.s))) return SPH_E_HIP;
+    return SPH_OK;
+}
+
+sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,
+                              const int32_t** ns, const int32_t** list, int64_t* stride)
+{
+    if (!config_ok(cfg)) return SPH_E_ARG;
+    if (!ws || ((uintptr_t)ws & 255)) return SPH_E_WORKSPACE;
+    Layout L = make_layout(cfg->n, cfg->ng_max);
+    Ws W = carve(ws, L);
+    if (nc) *nc = W.nc;
+    if (ns) *ns = W.ns;
+    if (list) *list = W.list;
+    if (stride) *stride = cfg->n;
+    return SPH_OK;
+}
+
+sph_status sph_order_view(const sph_config* cfg, void* ws, const uint64_t** keys,
+                          const uint32_t** perm)
+{
+    if (!config_ok(cfg)) return SPH_E_ARG;
+    if (!ws || ((uintptr_t)ws & 255)) return SPH_E_WORKSPACE;
+    Layout L = make_layout(cfg->n, cfg->ng_max);
+    Ws W = carve(ws, L);
+    if (keys) *keys = W.keys0;
+    if (perm) *perm = W.idx0;
+    return SPH_OK;
+}
+
+sph_status sph_status_sync(void* ws, sph_stream stream, uint32_t* bits)
+{
+    if (!ws || ((uintptr_t)ws & 255)) return SPH_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Domain* dom = (Domain*)ws;  // the domain record sits at offset 0
+    uint32_t word = 0;
+    if (hipMemcpyAsync(&word, &dom->err, sizeof word, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return SPH_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPH_E_HIP;
+    uint32_t zero = 0;
+    if (hipMemcpyAsync(&dom->err, &zero, sizeof zero, hipMemcpyHostToDevice, s) != hipSuccess)
+        return SPH_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPH_E_HIP;
+    if (bits) *bits = word;
+    if (word & SPH_ERRBIT_NONFINITE) return SPH_E_NONFINITE;
+    if (word & SPH_ERRBIT_SINGULAR_TAU) return SPH_E_SINGULAR_TAU;
+    if (word & SPH_ERRBIT_NEIGHBOR_OVERFLOW) return SPH_E_NEIGHBOR_OVERFLOW;
+    if (word & SPH_ERRBIT_CELL_RANGE) return SPH_E_CELL_RANGE;
+    return SPH_OK;
+}
+
+const char* sph_status_string(sph_status s)
+{
+    switch (s) {
+    case SPH_OK: return "SPH_OK";
+    case SPH_E_ARG: return "SPH_E_ARG: invalid argument";
+    case SPH_E_HIP: return "SPH_E_HIP: HIP launch or query failed";
+    case SPH_E_WORKSPACE: return "SPH_E_WORKSPACE: workspace NULL or not 256-byte aligned";
+    case SPH_E_NEIGHBOR_OVERFLOW: return "SPH_E_NEIGHBOR_OVERFLOW: a neighbour count exceeded ng_max";
+    case SPH_E_CELL_RANGE: return "SPH_E_CELL_RANGE: 4h reached the box length on a periodic axis";
+    case SPH_E_NONFINITE: return "SPH_E_NONFINITE: non-finite density or rate";
+    case SPH_E_SINGULAR_TAU: return "SPH_E_SINGULAR_TAU: IAD matrix not positive definite";
+    }
+    return "unknown sph_status";
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// sph_common.h -- internal declarations shared by the libsph HIP sources.
+//
+// Data layout in HBM (all caller-owned, see include/sph.h):
+//   * particle fields are structure-of-arrays FP64, one array per field, so a
+//     wavefront of 64 consecutive slots reads 512 contiguous bytes per field;
+//   * neighbour lists are int32 in column-major (ELL) layout, entry j of slot a
+//     at list[j*stride + a], so the 64 lanes of a wavefront reading entry j of
+//     their own targets hit 256 contiguous bytes;
+//   * the workspace holds the device-resident domain record, sort buffers, the
+//     dense cell table (start/end/max-h per Morton cell) and the lists.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph.h"
+
+namespace sph {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
+constexpr int kMaxLevel = 9;         // cell table holds at most 8^9 cells
+constexpr int kKeyBits = 21;         // bits per axis in the 63-bit key
+constexpr int kSumBlocks = 1024;     // fixed partition of the conservation sums
+constexpr int kMaxPermFields = 16;
+
+// ---------------------------------------------------------------- run parameters
+// POD copied by value into every kernel.
+struct Params {
+    int64_t n;
+    int64_t stride;        // list column stride (= n)
+    double box_lo[3], box_hi[3], L[3], halfL[3];
+    int periodic[3];
+    int sinc_n;
+    double bn;             // B_n normalisation of the sinc kernel
+    double n_target;
+    int ng_max;
+    int newton_iters;
+    double kappa;
+    int eos;
+    double gamma, c0, alpha;
+    double courant, growth, acc_dt, energy_dt;
+    int lcap;              // largest admissible cell level (8^lcap <= table size)
+    int precision;
+};
+
+// ---------------------------------------------------------------- device domain
+// Written on the device by sph_build_cells (and find_neighbors for hmax_new);
+// read by every later kernel, never by the host in the hot path.
+struct Domain {
+    double lo[3], hi[3];       // key domain: the box on periodic axes, bbox on open ones
+    double scale[3];           // 2^21 / (hi - lo), 0 on a zero-extent axis
+    double cell[3];            // cell edge (hi - lo) / 2^level
+    double hmax;               // largest h at build time
+    uint64_t hmax_new_bits;    // largest h after update_h (order-preserving bits)
+    uint64_t ord_min[3];       // order-preserving bits for the bbox reduction
+    uint64_t ord_max[3];
+    uint64_t ord_hmax;
+    uint64_t dtmin_bits;       // min_a h_a/c_a (bits of a positive double)
+    int32_t level, shift, ncell_axis;
+    uint32_t err;              // sticky SPH_ERRBIT_* word
+    int64_t built_n;
+};
+
+// ---------------------------------------------------------------- workspace layout
+struct Layout {
+    size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
+    size_t cstart, cend, chmax, nc, ns, list;
+    size_t total;
+    int64_t n, nsort_blocks, hist_len, scan_blocks, ncells_cap;
+    int lcap;
+};
+Layout make_layout(int64_t n, int ng_max);
+
+// device pointers carved out of ws
+struct Ws {
+    Domain* dom;
+    double* sums;
+    uint64_t *keys0, *keys1;
+    uint32_t *idx0, *idx1;
+    uint32_t* hist;
+    uint32_t* scanpart;
+    int32_t *cstart, *cend;
+    double* chmax;
+    int32_t *nc, *ns, *list;
+    double* tmp;               // permute scratch (aliases the list area)
+};
+Ws carve(void* ws, const Layout& L);
+
+// ---------------------------------------------------------------- device helpers
+#define SPH_DEV __device__ __forceinline__
+#define SPH_HD __host__ __device__ __forceinline__
+
+// map a double to uint64 bits whose unsigned order is the numeric order
+SPH_HD uint64_t ord_bits(double v)
+{
+    uint64_t b = __builtin_bit_cast(uint64_t, v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+SPH_HD double ord_value(uint64_t o)
+{
+    uint64_t b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+    return __builtin_bit_cast(double, b);
+}
+
+SPH_DEV void set_err(Domain* d, uint32_t bit) { atomicOr(&d->err, bit); }
+
+// spread the low 21 bits of v to every third bit (bit i -> bit 3i)
+SPH_HD uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x001f00000000ffffull;
+    v = (v | (v << 16)) & 0x001f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+SPH_HD uint64_t morton3(uint64_t qx, uint64_t qy, uint64_t qz)
+{
+    return (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+}
+
+// per-axis 21-bit coordinate (floor((x-lo)*scale), clamped to [0, 2^21-1])
+SPH_DEV uint32_t quantize(double x, double lo, double scale)
+{
+    if (!(scale > 0.0)) return 0u;
+    double t = x - lo;
+    double q = floor(t * scale);
+    if (!(q >= 0.0)) return 0u;
+    if (q > 2097151.0) return 2097151u;
+    return (uint32_t)q;
+}
+
+// displacement b - a with the minimum image, and r^2 in the fixed association
+// (dx*dx + dy*dy) + dz*dz (no contraction: the library is built with
+// -ffp-contract=off, so the neighbour test rounds the same everywhere)
+SPH_DEV double disp(const Params& P, double xa, double ya, double za, double xb, double yb,
+                    double zb, double& dx, double& dy, double& dz)
+{
+    dx = xb - xa;
+    dy = yb - ya;
+    dz = zb - za;
+    if (P.periodic[0]) { if (dx > P.halfL[0]) dx -= P.L[0]; else if (dx <= -P.halfL[0]) dx += P.L[0]; }
+    if (P.periodic[1]) { if (dy > P.halfL[1]) dy -= P.L[1]; else if (dy <= -P.halfL[1]) dy += P.L[1]; }
+    if (P.periodic[2]) { if (dz > P.halfL[2]) dz -= P.L[2]; else if (dz <= -P.halfL[2]) dz += P.L[2]; }
+    double r2 = dx * dx;
+    r2 = r2 + dy * dy;
+    r2 = r2 + dz * dz;
+    return r2;
+}
+
+// ------------------------------------------------------------- sinc kernel
+// With x = (pi/2) v and t = x^2 the kernel needs only even power series in t:
+//   sinc(x)          = sum_{k>=0} (-1)^k t^k / (2k+1)!
+//   x sinc'(x)       = cos x - sinc x = sum_{k>=1} (-1)^k 2k t^k / (2k+1)!
+// (Taylor series; 16 terms reach double precision on 0 <= x <= pi since
+// pi^30/31! < 1e-18).  No sqrt, sin or division per pair.
+constexpr int kSincTerms = 16;
+struct SincTable {
+    double s[kSincTerms];   // coefficient of t^k in sinc
+    double d[kSincTerms];   // coefficient of t^(k+1) in x sinc'(x)
+    constexpr SincTable() : s(), d()
+    {
+        double c = 1.0;  // (-1)^k / (2k+1)!
+        for (int k = 0; k < kSincTerms; ++k) {
+            if (k > 0) c = -c / ((2.0 * k) * (2.0 * k + 1.0));
+            s[k] = c;
+        }
+        // coefficient of t^(k+1) in x sinc'(x) is 2(k+1) times that of t^(k+1) in sinc
+        for (int k = 0; k + 1 < kSincTerms; ++k) d[k] = 2.0 * (k + 1) * s[k + 1];
+        d[kSincTerms - 1] = 0.0;
+    }
+};
+constexpr SincTable kSinc{};
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kPiHalfSq = (kPi * kPi) / 4.0;
+
+// S_n and v dS_n/dv at t = (pi/2)^2 v^2, integer n >= 1
+SPH_DEV void sinc_terms(double t, int n, double& S, double& vdS)
+{
+    double s = kSinc.s[kSincTerms - 1];
+#pragma unroll
+    for (int k = kSincTerms - 2; k >= 0; --k) s = fma(s, t, kSinc.s[k]);
+    double q = kSinc.d[kSincTerms - 2];
+#pragma unroll
+    for (int k = kSincTerms - 3; k >= 0; --k) q = fma(q, t, kSinc.d[k]);
+    q = q * t;                      // x sinc'(x)
+    double p = 1.0;                 // s^(n-1)
+    for (int i = 1; i < n; ++i) p = p * s;
+    S = p * s;
+    vdS = (double)n * p * q;
+}
+
+SPH_DEV double sinc_S(double t, int n)
+{
+    double s = kSinc.s[kSincTerms - 1];
+#pragma unroll
+    for (int k = kSincTerms - 2; k >= 0; --k) s = fma(s, t, kSinc.s[k]);
+    double p = s;
+    for (int i = 1; i < n; ++i) p = p * s;
+    return p;
+}
+
+// ------------------------------------------------------------- launch helpers
+// The hardware hands workgroup i to XCD (i mod 8); remap so that each XCD
+// works on one contiguous range of slots (spatially close particles share the
+// XCD's L2).  Launch grid_xcd(nb) groups; returns -1 for padding groups.
+constexpr int kXcds = 8;
+inline int64_t grid_xcd(int64_t nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
+SPH_DEV int64_t xcd_block(int64_t nb)
+{
+    int64_t bid = blockIdx.x;
+    int64_t per = (nb + kXcds - 1) / kXcds;
+    int64_t lb = (bid % kXcds) * per + bid / kXcds;
+    return lb < nb ? lb : -1;
+}
+
+// ------------------------------------------------------------- host launchers
+Params make_params(const sph_config* cfg, double bn, int lcap);
+double sinc_bn(int n);   // host: B_n normalisation
+
+hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
+                              const sph_particles* p, hipStream_t s);
+hipError_t launch_update_h(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                           hipStream_t s);
+hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
+                                 const sph_particles* p, hipStream_t s);
+hipError_t launch_density(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                          hipStream_t s);
+hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                      hipStream_t s);
+hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
+                                  sph_particles* p, hipStream_t s);
+hipError_t launch_timestep(const Params& P, const Ws& W, sph_globals* g, hipStream_t s);
+hipError_t launch_integrate(const Params& P, const Ws& W, sph_particles* p, sph_globals* g,
+                            hipStream_t s);
+hipError_t launch_clear_domain(const Ws& W, hipStream_t s);
+
+}  // namespace sph

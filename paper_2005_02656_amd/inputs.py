@@ -52,7 +52,7 @@ def base_params(**kw) -> dict:
     p = dict(box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0), periodic=(1, 1, 1),
              sinc_n=6.0, n_target=100.0, newton_iters=2, h_ratio_max=1.25, eos=0,
              gamma=5.0 / 3.0, c0=0.0, alpha_av=1.0, courant=0.2, dt_growth=1.1,
-             ng_max=160)
+             acc_dt=0.2, energy_dt=0.2, ng_max=160)
     p.update(kw)
     return p
 
@@ -100,7 +100,7 @@ def square_patch(n_side: int, omega: float = 5.0, u0: float = 1.0) -> Workload:
                p_ref=p_ref)
     c0 = 10.0 * omega * np.sqrt(2.0) / 2.0
     prm = base_params(box_lo=(-0.5, -0.5, -0.5), box_hi=(0.5, 0.5, 0.5), periodic=(0, 0, 1),
-                      eos=1, c0=c0)
+                      eos=1, c0=c0, energy_dt=0.0)
     return Workload(f"square_patch{n_side}^3", arr, prm)
 
 

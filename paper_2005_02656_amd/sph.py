@@ -1,0 +1,330 @@
+"""ctypes binding of libsph (include/sph.h).
+
+Argument marshalling only: torch tensors provide device memory and the stream,
+every step of the SPH path runs in the library's HIP kernels.  The library must
+be built (``python -m paper_2005_02656_amd.build``); if it is missing this module
+raises on first use -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsph.so")
+
+SPH_OK = 0
+STATUS_NAMES = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_WORKSPACE",
+                4: "SPH_E_NEIGHBOR_OVERFLOW", 5: "SPH_E_CELL_RANGE", 6: "SPH_E_NONFINITE",
+                7: "SPH_E_SINGULAR_TAU"}
+ERRBIT_NEIGHBOR_OVERFLOW, ERRBIT_CELL_RANGE, ERRBIT_NONFINITE, ERRBIT_SINGULAR_TAU = 1, 2, 4, 8
+FP64, MIXED = 0, 1
+
+STATE_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",
+                "p_ref", "rho_ref")
+OUT_FIELDS = ("rho", "omega", "p", "c", "c11", "c12", "c13", "c22", "c23", "c33", "ax", "ay",
+              "az", "du")
+GLOBAL_FIELDS = ("dt", "dt_m1", "t", "mass", "mom0", "mom1", "mom2", "ang0", "ang1", "ang2",
+                 "e_kin", "e_int")
+
+
+class SphError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}")
+
+
+class _Config(C.Structure):
+    _fields_ = [("n", C.c_int64), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+                ("periodic", C.c_int32 * 3), ("eos", C.c_int32), ("sinc_n", C.c_double),
+                ("n_target", C.c_double), ("ng_max", C.c_int32), ("newton_iters", C.c_int32),
+                ("h_ratio_max", C.c_double), ("gamma", C.c_double), ("c0", C.c_double),
+                ("alpha_av", C.c_double), ("courant", C.c_double), ("dt_growth", C.c_double),
+                ("acc_dt", C.c_double), ("energy_dt", C.c_double),
+                ("precision", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Particles(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in
+                ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",
+                 "p_ref", "rho_ref", "id") + OUT_FIELDS]
+
+
+@dataclasses.dataclass
+class Config:
+    n: int
+    box_lo: tuple = (0.0, 0.0, 0.0)
+    box_hi: tuple = (1.0, 1.0, 1.0)
+    periodic: tuple = (1, 1, 1)
+    eos: int = 0
+    sinc_n: float = 6.0
+    n_target: float = 100.0
+    ng_max: int = 160
+    newton_iters: int = 2
+    h_ratio_max: float = 1.25
+    gamma: float = 5.0 / 3.0
+    c0: float = 0.0
+    alpha_av: float = 1.0
+    courant: float = 0.2
+    dt_growth: float = 1.1
+    acc_dt: float = 0.2
+    energy_dt: float = 0.2
+    precision: int = FP64
+
+    @classmethod
+    def from_params(cls, n: int, params: dict, **kw) -> "Config":
+        keys = set(cls.__dataclass_fields__)
+        p = {k: v for k, v in params.items() if k in keys}
+        p.update(kw)
+        return cls(n=n, **p)
+
+    def replace(self, **kw) -> "Config":
+        return dataclasses.replace(self, **kw)
+
+    def c(self) -> _Config:
+        s = _Config()
+        s.n = int(self.n)
+        s.box_lo[:] = [float(v) for v in self.box_lo]
+        s.box_hi[:] = [float(v) for v in self.box_hi]
+        s.periodic[:] = [int(v) for v in self.periodic]
+        s.eos = int(self.eos)
+        s.sinc_n = float(self.sinc_n)
+        s.n_target = float(self.n_target)
+        s.ng_max = int(self.ng_max)
+        s.newton_iters = int(self.newton_iters)
+        s.h_ratio_max = float(self.h_ratio_max)
+        s.gamma = float(self.gamma)
+        s.c0 = float(self.c0)
+        s.alpha_av = float(self.alpha_av)
+        s.courant = float(self.courant)
+        s.dt_growth = float(self.dt_growth)
+        s.acc_dt = float(self.acc_dt)
+        s.energy_dt = float(self.energy_dt)
+        s.precision = int(self.precision)
+        s.reserved = 0
+        return s
+
+
+_lib = None
+_SIGS = {
+    "sph_workspace_bytes": (C.c_size_t, [C.c_void_p]),
+    "sph_workspace_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_build_cells": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_update_h": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_find_neighbors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_iad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_momentum_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_timestep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_integrate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_neighbors_view": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "sph_order_view": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_status_sync": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_status_string": (C.c_char_p, [C.c_int]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Loads libsph.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2005_02656_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _check(st, what):
+    if st != SPH_OK:
+        raise SphError(st, what)
+
+
+# --------------------------------------------------------------------------- memory
+class Workspace:
+    """Caller-owned workspace (a torch uint8 tensor, 256-byte aligned)."""
+
+    def __init__(self, cfg: Config, device="cuda"):
+        nbytes = lib().sph_workspace_bytes(C.byref(cfg.c()))
+        if nbytes == 0:
+            raise SphError(1, "sph_workspace_bytes (invalid config)")
+        self.raw = torch.zeros(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.raw.data_ptr()) % 256
+        self.buf = self.raw[off:off + nbytes]
+        self.nbytes = nbytes
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+    def view(self, ptr: int, count: int, dtype) -> torch.Tensor:
+        """Tensor view of `count` elements of dtype at device address ptr inside ws."""
+        off = ptr - self.buf.data_ptr()
+        esz = torch.empty((), dtype=dtype).element_size()
+        if off < 0 or off + count * esz > self.nbytes:
+            raise ValueError("view outside the workspace")
+        return self.buf[off:off + count * esz].view(dtype)
+
+
+class Particles:
+    """Device arrays of one particle set (torch tensors, FP64 SoA; id int64)."""
+
+    def __init__(self, tensors: dict):
+        self.t = tensors
+
+    @classmethod
+    def from_arrays(cls, arrays: dict, cfg: Config, device="cuda") -> "Particles":
+        n = cfg.n
+        t = {}
+        for k in ("x", "y", "z", "vx", "vy", "vz", "h", "m", "u"):
+            t[k] = torch.as_tensor(arrays[k], dtype=torch.float64).to(device).contiguous()
+        for k, src in (("vhx", "vx"), ("vhy", "vy"), ("vhz", "vz")):
+            t[k] = torch.as_tensor(arrays.get(k, arrays[src]), dtype=torch.float64).to(device).clone()
+        if "du_m1" in arrays:
+            t["du_m1"] = torch.as_tensor(arrays["du_m1"], dtype=torch.float64).to(device).clone()
+        else:
+            t["du_m1"] = torch.zeros(n, dtype=torch.float64, device=device)
+        t["id"] = torch.as_tensor(arrays["id"], dtype=torch.int64).to(device).contiguous()
+        if cfg.eos == 1:
+            t["p_ref"] = torch.as_tensor(arrays["p_ref"], dtype=torch.float64).to(device).contiguous()
+            t["rho_ref"] = (torch.as_tensor(arrays["rho_ref"], dtype=torch.float64).to(device)
+                            .contiguous() if "rho_ref" in arrays
+                            else torch.zeros(n, dtype=torch.float64, device=device))
+        for k in OUT_FIELDS:
+            t[k] = torch.zeros(n, dtype=torch.float64, device=device)
+        for k, v in t.items():
+            if v.numel() != n:
+                raise ValueError(f"field {k} has {v.numel()} entries, expected {n}")
+        return cls(t)
+
+    def __getitem__(self, k):
+        return self.t[k]
+
+    def __setitem__(self, k, v):
+        self.t[k].copy_(v)
+
+    def c(self) -> _Particles:
+        s = _Particles()
+        for name, _ in _Particles._fields_:
+            v = self.t.get(name)
+            setattr(s, name, C.c_void_p(v.data_ptr()) if v is not None else None)
+        return s
+
+
+class Globals:
+    """The 14 device doubles of sph_globals."""
+
+    def __init__(self, device="cuda"):
+        self.t = torch.zeros(14, dtype=torch.float64, device=device)
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.t.data_ptr())
+
+    def host(self) -> dict:
+        v = self.t.cpu().tolist()
+        return {"dt": v[0], "dt_m1": v[1], "t": v[2], "mass": v[3], "mom": v[4:7],
+                "ang": v[7:10], "e_kin": v[10], "e_int": v[11]}
+
+
+# --------------------------------------------------------------------------- entry points
+def workspace_init(cfg: Config, ws: Workspace, stream=None):
+    _check(lib().sph_workspace_init(C.byref(cfg.c()), ws.ptr, _stream(stream)), "sph_workspace_init")
+
+
+def _stage(name):
+    def f(cfg: Config, parts: Particles, ws: Workspace, stream=None):
+        ps = parts.c()
+        _check(getattr(lib(), name)(C.byref(cfg.c()), C.byref(ps), ws.ptr, _stream(stream)), name)
+    f.__name__ = name[4:]
+    f.__doc__ = f"Enqueues {name} (see include/sph.h)."
+    return f
+
+
+build_cells = _stage("sph_build_cells")
+update_h = _stage("sph_update_h")
+find_neighbors = _stage("sph_find_neighbors")
+density = _stage("sph_density")
+iad = _stage("sph_iad")
+momentum_energy = _stage("sph_momentum_energy")
+
+
+def timestep(cfg: Config, g: Globals, ws: Workspace, stream=None):
+    _check(lib().sph_timestep(C.byref(cfg.c()), g.ptr, ws.ptr, _stream(stream)), "sph_timestep")
+
+
+def integrate(cfg: Config, parts: Particles, g: Globals, ws: Workspace, stream=None):
+    ps = parts.c()
+    _check(lib().sph_integrate(C.byref(cfg.c()), C.byref(ps), g.ptr, ws.ptr, _stream(stream)),
+           "sph_integrate")
+
+
+def step(cfg: Config, parts: Particles, g: Globals, ws: Workspace, stream=None):
+    ps = parts.c()
+    _check(lib().sph_step(C.byref(cfg.c()), C.byref(ps), g.ptr, ws.ptr, _stream(stream)),
+           "sph_step")
+
+
+def neighbors_view(cfg: Config, ws: Workspace):
+    """Returns (nc, ns, list) tensor views into ws; list has shape (ng_max, n)."""
+    nc, ns, lst = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    stride = C.c_int64()
+    _check(lib().sph_neighbors_view(C.byref(cfg.c()), ws.ptr, C.byref(nc), C.byref(ns),
+                                    C.byref(lst), C.byref(stride)), "sph_neighbors_view")
+    n = cfg.n
+    return (ws.view(nc.value, n, torch.int32), ws.view(ns.value, n, torch.int32),
+            ws.view(lst.value, cfg.ng_max * stride.value, torch.int32).view(cfg.ng_max,
+                                                                              stride.value))
+
+
+def order_view(cfg: Config, ws: Workspace):
+    """Returns (keys uint64-as-int64, perm int32) views into ws."""
+    k, p = C.c_void_p(), C.c_void_p()
+    _check(lib().sph_order_view(C.byref(cfg.c()), ws.ptr, C.byref(k), C.byref(p)),
+           "sph_order_view")
+    return ws.view(k.value, cfg.n, torch.int64), ws.view(p.value, cfg.n, torch.int32)
+
+
+def status_sync(ws: Workspace, stream=None):
+    """Synchronises the stream; returns (status, bits) and clears the device word."""
+    bits = C.c_uint32()
+    st = lib().sph_status_sync(ws.ptr, _stream(stream), C.byref(bits))
+    return st, bits.value
+
+
+def status_string(st: int) -> str:
+    return lib().sph_status_string(int(st)).decode()
+
+
+# --------------------------------------------------------------------------- set-up
+def initialise(cfg: Config, parts: Particles, ws: Workspace, g: Globals, iters: int = 12,
+               kappa: float = 8.0, stream=None):
+    """Untimed set-up of a workload: `iters` Newton steps on h from the generator's
+    guess (clamped at [h/kappa, kappa h]); with the weakly compressible EOS the
+    reference density rho_ref is the density at t = 0.  Leaves the particles in
+    key order and the globals at t = 0 with no previous step."""
+    workspace_init(cfg, ws, stream)
+    build_cells(cfg, parts, ws, stream)
+    update_h(cfg.replace(newton_iters=iters, h_ratio_max=kappa), parts, ws, stream)
+    if cfg.eos == 1:
+        find_neighbors(cfg, parts, ws, stream)
+        density(cfg, parts, ws, stream)
+        parts.t["rho_ref"].copy_(parts.t["rho"])
+    g.t.zero_()

@@ -87,10 +87,22 @@ def test_periodic_wrap(ora):
 
 
 def test_timestep_rule(ora):
-    cfg = oracle_config(inputs.base_params())
+    cfg = oracle_config(inputs.base_params(), acc_dt=0.0, energy_dt=0.0)
     h = np.array([0.1, 0.05, 0.2])
     c = np.array([1.0, 2.0, 0.5])
-    assert ora.timestep(cfg, h, c, 0.0) == pytest.approx(0.2 * 0.025, rel=1e-15)
+    z = np.zeros(3)
+    u = np.ones(3)
+    assert ora.timestep(cfg, h, c, u, z, z, z, z, 0.0) == pytest.approx(0.2 * 0.025, rel=1e-15)
     # growth limit 1.1 x previous
-    assert ora.timestep(cfg, h, c, 0.001) == pytest.approx(0.0011, rel=1e-15)
-    assert ora.timestep(cfg, h, c, 1.0) == pytest.approx(0.005, rel=1e-15)
+    assert ora.timestep(cfg, h, c, u, z, z, z, z, 0.001) == pytest.approx(0.0011, rel=1e-15)
+    assert ora.timestep(cfg, h, c, u, z, z, z, z, 1.0) == pytest.approx(0.005, rel=1e-15)
+    # acceleration criterion: |a| = 5 at h = 0.2 gives 0.2 sqrt(0.2/5) = 0.04 ...
+    ca = cfg.replace(acc_dt=0.2)
+    ax = np.array([0.0, 0.0, 3.0])
+    ay = np.array([0.0, 0.0, 4.0])
+    c2 = np.array([1e-3, 1e-3, 1e-3])    # slow sound: Courant would give 4.0+
+    assert ora.timestep(ca, h, c2, u, ax, ay, z, z, 0.0) == pytest.approx(0.04, rel=1e-15)
+    # ... and the energy criterion |u|/|du| = 1/50 gives 0.004
+    ce = ca.replace(energy_dt=0.2)
+    du = np.array([0.0, -50.0, 0.0])
+    assert ora.timestep(ce, h, c2, u, ax, ay, z, du, 0.0) == pytest.approx(0.004, rel=1e-15)
