@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-stage-timing", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=32,
                     help="side of the square-patch lattice the oracle steps on")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (scales HBM counters)")
     return ap.parse_args()
 
 
@@ -216,6 +218,18 @@ def main():
                                               f"particle x {n} particles"}
         step_bytes = sum(bytes_per_particle(s, k_g, k_s, wc) for s in stt) * n
         out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE counters calibrate
+        # the byte counters of the SPH kernels in the same profiled run
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nbytes
+        del src, dst
 
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")

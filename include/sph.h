@@ -182,18 +182,27 @@ sph_status sph_integrate(const sph_config* cfg, sph_particles* p, sph_globals* g
 
 /* One full time step: build_cells, update_h, find_neighbors, density, iad,
  * momentum_energy, timestep, integrate (the step order follows the three halo
- * refreshes of section 4.4 and the global reductions of section 4.2). */
+ * refreshes of section 4.4 and the global reductions of section 4.2).
+ * With h_ratio_max <= 1.25 the h update and the neighbour search share one cell
+ * walk: it collects candidates within 2*h_ratio_max*max(h_a, h_b) (every pair
+ * the clamped Newton steps and the lists can need), the Newton sums run over
+ * the candidates and the lists are filtered from them; the results are the
+ * ones of the separate stages (same sets, other summation order).  The
+ * workspace holds ceil(1.25^4 * ng_max) candidate slots
+ * per particle; a candidate overflow sets SPH_ERRBIT_NEIGHBOR_OVERFLOW. */
 sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
                     sph_stream stream);
 
-/* (host) Views into ws after sph_find_neighbors: nc, ns (int32[n]) and the list
- * (int32, column-major: entry j of slot a at list[j*stride + a]).  Slot a's
- * gather neighbours are at j = 0..nc[a]-1; its symmetric-only neighbours
- * (in N_s(a) but not N(a)) are at j = ng_max-(ns[a]-nc[a]) .. ng_max-1.
+/* (host) Device pointers into ws after sph_find_neighbors or sph_step: nc, ns
+ * (int32[n]) and the list (int32, tiled by 64 slots so that a wavefront's
+ * entries are contiguous: entry j of slot a is at
+ *     list[((a/64)*capacity + j)*64 + a%64],   capacity = ng_max).
+ * Slot a's gather neighbours are at j = 0..nc[a]-1; its symmetric-only
+ * neighbours (in N_s(a) but not N(a)) are at j = ng_max-(ns[a]-nc[a]) .. ng_max-1.
  * Entries are slot indices.  Counts are true counts even when they exceed
  * ng_max (then SPH_ERRBIT_NEIGHBOR_OVERFLOW is set and the lists truncated). */
 sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,
-                              const int32_t** ns, const int32_t** list, int64_t* stride);
+                              const int32_t** ns, const int32_t** list, int32_t* capacity);
 
 /* (host) Device pointers into ws after sph_build_cells: the sorted keys
  * (uint64[n]) and the permutation perm (uint32[n], slot -> slot before the call). */

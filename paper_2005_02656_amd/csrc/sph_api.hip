@@ -31,14 +31,22 @@ Layout make_layout(int64_t n, int ng_max)
     L.idx1 = take(sizeof(uint32_t) * n);
     L.hist = take(sizeof(uint32_t) * L.hist_len);
     L.scanpart = take(sizeof(uint32_t) * (L.scan_blocks + 1));
-    L.cstart = take(sizeof(int32_t) * L.ncells_cap);
-    L.cend = take(sizeof(int32_t) * L.ncells_cap);
-    L.chmax = take(sizeof(double) * L.ncells_cap);
+    L.cells = take(sizeof(CellRange) * L.ncells_cap);
     L.nc = take(sizeof(int32_t) * n);
     L.ns = take(sizeof(int32_t) * n);
-    size_t lst = sizeof(int32_t) * (size_t)ng_max * n;
+    L.nk = take(sizeof(int32_t) * n);
+    L.p4 = take(sizeof(Pos4) * n);
+    L.rec = take(sizeof(MomRec) * n);
+    L.vol = take(sizeof(double) * n);
+    const size_t padded = (size_t)((n + 63) / 64) * 64;   // lists are tiled by 64 slots
+    size_t lst = sizeof(int32_t) * (size_t)ng_max * padded;
     size_t tmp = sizeof(double) * kMaxPermFields * n;
     L.list = take(lst > tmp ? lst : tmp);
+    L.cand_cap = candidate_capacity(ng_max);
+    L.cand = take(sizeof(int32_t) * (size_t)L.cand_cap * padded);
+    L.posm = take(mixed_posm_bytes() * n);
+    L.mf = take(sizeof(float) * n);
+    L.mf2 = take(sizeof(float) * n);
     L.total = o;
     return L;
 }
@@ -55,11 +63,18 @@ Ws carve(void* ws, const Layout& L)
     W.idx1 = (uint32_t*)(b + L.idx1);
     W.hist = (uint32_t*)(b + L.hist);
     W.scanpart = (uint32_t*)(b + L.scanpart);
-    W.cstart = (int32_t*)(b + L.cstart);
-    W.cend = (int32_t*)(b + L.cend);
-    W.chmax = (double*)(b + L.chmax);
+    W.cells = (CellRange*)(b + L.cells);
     W.nc = (int32_t*)(b + L.nc);
     W.ns = (int32_t*)(b + L.ns);
+    W.nk = (int32_t*)(b + L.nk);
+    W.cand = (int32_t*)(b + L.cand);
+    W.posm = (void*)(b + L.posm);
+    W.recm = (void*)(b + L.rec);   // FP32 records use the first half of the FP64 record area
+    W.mf = (float*)(b + L.mf);
+    W.mf2 = (float*)(b + L.mf2);
+    W.p4 = (Pos4*)(b + L.p4);
+    W.rec = (MomRec*)(b + L.rec);
+    W.vol = (double*)(b + L.vol);
     W.list = (int32_t*)(b + L.list);
     W.tmp = (double*)(b + L.list);
     return W;
@@ -103,11 +118,10 @@ const BnTable kBn;  // constant after load
 
 double sinc_bn(int n) { return (n >= 3 && n <= 9) ? kBn.v[n] : 0.0; }
 
-Params make_params(const sph_config* cfg, double bn, int lcap)
+Params make_params(const sph_config* cfg, double bn, int lcap, int cand_cap)
 {
     Params P{};
     P.n = cfg->n;
-    P.stride = cfg->n;
     for (int k = 0; k < 3; ++k) {
         P.box_lo[k] = cfg->box_lo[k];
         P.box_hi[k] = cfg->box_hi[k];
@@ -130,6 +144,7 @@ Params make_params(const sph_config* cfg, double bn, int lcap)
     P.acc_dt = cfg->acc_dt;
     P.energy_dt = cfg->energy_dt;
     P.lcap = lcap;
+    P.cand_cap = cand_cap;
     P.precision = cfg->precision;
     return P;
 }
@@ -187,7 +202,8 @@ sph_status prepare(const sph_config* cfg, void* ws, sph_stream stream, Ctx& c)
     if (!ws || ((uintptr_t)ws & 255)) return SPH_E_WORKSPACE;
     c.L = make_layout(cfg->n, cfg->ng_max);
     c.W = carve(ws, c.L);
-    c.P = make_params(cfg, sinc_bn((int)cfg->sinc_n), c.L.lcap);
+    const bool fused = cfg->h_ratio_max <= kFusedKappaMax;
+    c.P = make_params(cfg, sinc_bn((int)cfg->sinc_n), c.L.lcap, fused ? c.L.cand_cap : 0);
     c.s = (hipStream_t)stream;
     return SPH_OK;
 }
@@ -227,7 +243,7 @@ sph_status sph_update_h(const sph_config* cfg, sph_particles* p, void* ws, sph_s
     sph_status st = prepare(cfg, ws, stream, c);
     if (st) return st;
     if (!p || !p->x || !p->y || !p->z || !p->h) return SPH_E_ARG;
-    return hip_status(launch_update_h(c.P, c.L, c.W, p, c.s));
+    return hip_status(launch_update_h(c.P, c.L, c.W, p, c.s, true));
 }
 
 sph_status sph_find_neighbors(const sph_config* cfg, const sph_particles* p, void* ws,
@@ -249,7 +265,9 @@ sph_status sph_density(const sph_config* cfg, sph_particles* p, void* ws, sph_st
         !p->p || !p->c)
         return SPH_E_ARG;
     if (cfg->eos == SPH_EOS_WEAKLY_COMPRESSIBLE && (!p->p_ref || !p->rho_ref)) return SPH_E_ARG;
-    return hip_status(launch_density(c.P, c.L, c.W, p, c.s));
+    if (c.P.precision == SPH_MIXED)
+        return hip_status(launch_density_mixed(c.P, c.L, c.W, p, c.s, true));
+    return hip_status(launch_density(c.P, c.L, c.W, p, c.s, true));
 }
 
 sph_status sph_iad(const sph_config* cfg, sph_particles* p, void* ws, sph_stream stream)
@@ -260,7 +278,9 @@ sph_status sph_iad(const sph_config* cfg, sph_particles* p, void* ws, sph_stream
     if (!p || !p->x || !p->y || !p->z || !p->h || !p->m || !p->rho || !p->c11 || !p->c12 ||
         !p->c13 || !p->c22 || !p->c23 || !p->c33)
         return SPH_E_ARG;
-    return hip_status(launch_iad(c.P, c.L, c.W, p, c.s));
+    if (c.P.precision == SPH_MIXED)
+        return hip_status(launch_iad_mixed(c.P, c.L, c.W, p, c.s, true, false));
+    return hip_status(launch_iad(c.P, c.L, c.W, p, c.s, true, false));
 }
 
 sph_status sph_momentum_energy(const sph_config* cfg, sph_particles* p, void* ws,
@@ -273,7 +293,9 @@ sph_status sph_momentum_energy(const sph_config* cfg, sph_particles* p, void* ws
         !p->u || !p->rho || !p->omega || !p->p || !p->c || !p->c11 || !p->c12 || !p->c13 || !p->c22 ||
         !p->c23 || !p->c33 || !p->ax || !p->ay || !p->az || !p->du)
         return SPH_E_ARG;
-    return hip_status(launch_momentum_energy(c.P, c.L, c.W, p, c.s));
+    if (c.P.precision == SPH_MIXED)
+        return hip_status(launch_momentum_energy_mixed(c.P, c.L, c.W, p, c.s, true));
+    return hip_status(launch_momentum_energy(c.P, c.L, c.W, p, c.s, true));
 }
 
 sph_status sph_timestep(const sph_config* cfg, sph_globals* g, void* ws, sph_stream stream)
@@ -307,18 +329,31 @@ sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, voi
         return SPH_E_ARG;
     hipError_t e;
     if ((e = launch_build_cells(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    if ((e = launch_update_h(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    if ((e = launch_find_neighbors(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    if ((e = launch_density(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    if ((e = launch_iad(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    if ((e = launch_momentum_energy(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    // the cell build packs positions; with a small clamp ratio one cell walk
+    // feeds both the Newton iterations and the lists (fused), else the walks of
+    // the stage entry points run; the IAD pass writes the momentum records
+    if (c.P.cand_cap > 0) {
+        if ((e = launch_fused_h_lists(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    } else {
+        if ((e = launch_update_h(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+        if ((e = launch_find_neighbors(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    }
+    if (c.P.precision == SPH_MIXED) {
+        if ((e = launch_density_mixed(c.P, c.L, c.W, p, c.s, true))) return SPH_E_HIP;
+        if ((e = launch_iad_mixed(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
+        if ((e = launch_momentum_energy_mixed(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+    } else {
+        if ((e = launch_density(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+        if ((e = launch_iad(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
+        if ((e = launch_momentum_energy(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+    }
     if ((e = launch_timestep(c.P, c.W, g, c.s))) return SPH_E_HIP;
     if ((e = launch_integrate(c.P, c.W, p, g, c.s))) return SPH_E_HIP;
     return SPH_OK;
 }
 
 sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,
-                              const int32_t** ns, const int32_t** list, int64_t* stride)
+                              const int32_t** ns, const int32_t** list, int32_t* capacity)
 {
     if (!config_ok(cfg)) return SPH_E_ARG;
     if (!ws || ((uintptr_t)ws & 255)) return SPH_E_WORKSPACE;
@@ -327,7 +362,7 @@ sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** n
     if (nc) *nc = W.nc;
     if (ns) *ns = W.ns;
     if (list) *list = W.list;
-    if (stride) *stride = cfg->n;
+    if (capacity) *capacity = cfg->ng_max;
     return SPH_OK;
 }
 

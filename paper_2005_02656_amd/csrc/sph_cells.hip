@@ -23,7 +23,12 @@ constexpr int kSortTile = kBlock * kSortItems;      // 4096
 constexpr int kWaves = kBlock / 64;
 constexpr int kWaveItems = kSortTile / kWaves;      // 1024 consecutive keys per wave
 constexpr int kRedGrid = 1024;                      // bbox reduction blocks
-constexpr double kCellFactor = 1.0;                 // cell edge >= kCellFactor * hmax
+#ifndef SPH_CELL_FACTOR
+#define SPH_CELL_FACTOR 0.5
+#endif
+// cell edge >= kCellFactor * hmax: cells smaller than the kernel reach, walked
+// with a per-target stencil and per-cell distance culling
+constexpr double kCellFactor = SPH_CELL_FACTOR;
 
 __global__ void k_clear_domain(Domain* d)
 {
@@ -318,21 +323,18 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
 
 // ------------------------------------------------------------------ cell table
 __global__ __launch_bounds__(kBlock) void k_cells_clear(const Domain* __restrict__ d,
-                                                        int32_t* __restrict__ cs,
-                                                        int32_t* __restrict__ ce, int64_t cap)
+                                                        CellRange* __restrict__ cells,
+                                                        int64_t cap)
 {
     int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     int64_t ncell = int64_t(1) << (3 * d->level);
-    if (c < ncell && c < cap) {
-        cs[c] = 0;
-        ce[c] = 0;
-    }
+    if (c < ncell && c < cap) cells[c] = CellRange{0, 0};
 }
 
 __global__ __launch_bounds__(kBlock) void k_cells_fill(const Domain* __restrict__ d,
                                                        const uint64_t* __restrict__ keys,
-                                                       int64_t n, int32_t* __restrict__ cs,
-                                                       int32_t* __restrict__ ce)
+                                                       int64_t n,
+                                                       CellRange* __restrict__ cells)
 {
     int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
@@ -340,8 +342,8 @@ __global__ __launch_bounds__(kBlock) void k_cells_fill(const Domain* __restrict_
     uint64_t c = (sh >= 64) ? 0ull : (keys[i] >> sh);
     uint64_t cp = (i > 0) ? ((sh >= 64) ? 0ull : (keys[i - 1] >> sh)) : ~0ull;
     uint64_t cn = (i + 1 < n) ? ((sh >= 64) ? 0ull : (keys[i + 1] >> sh)) : ~0ull;
-    if (cp != c) cs[c] = (int32_t)i;
-    if (cn != c) ce[c] = (int32_t)(i + 1);
+    if (cp != c) cells[c].s = (int32_t)i;
+    if (cn != c) cells[c].e = (int32_t)(i + 1);
 }
 
 // ------------------------------------------------------------------ permutation
@@ -362,13 +364,31 @@ __global__ __launch_bounds__(kBlock) void k_gather(PermSet S, const uint32_t* __
     for (int f = 0; f < S.nf; ++f) tmp[(int64_t)f * n + i] = S.f[f][src];
 }
 
+// copy back, and pack positions and h (fields 0, 1, 2 and 9 of the set)
 __global__ __launch_bounds__(kBlock) void k_scatter_back(PermSet S,
                                                          const uint64_t* __restrict__ tmp,
-                                                         int64_t n)
+                                                         int64_t n, Pos4* __restrict__ p4)
 {
     int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
     for (int f = 0; f < S.nf; ++f) S.f[f][i] = tmp[(int64_t)f * n + i];
+    Pos4 q;
+    q.x = __builtin_bit_cast(double, tmp[i]);
+    q.y = __builtin_bit_cast(double, tmp[n + i]);
+    q.z = __builtin_bit_cast(double, tmp[2 * n + i]);
+    q.h = __builtin_bit_cast(double, tmp[9 * n + i]);
+    p4[i] = q;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_p4(const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ z,
+                                                    const double* __restrict__ h, int64_t n,
+                                                    Pos4* __restrict__ p4)
+{
+    int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    p4[i] = Pos4{x[i], y[i], z[i], h[i]};
 }
 
 }  // namespace
@@ -408,8 +428,8 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
     }
 
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
-    k_cells_clear<<<cb, kBlock, 0, s>>>(W.dom, W.cstart, W.cend, L.ncells_cap);
-    k_cells_fill<<<nb, kBlock, 0, s>>>(W.dom, W.keys0, n, W.cstart, W.cend);
+    k_cells_clear<<<cb, kBlock, 0, s>>>(W.dom, W.cells, L.ncells_cap);
+    k_cells_fill<<<nb, kBlock, 0, s>>>(W.dom, W.keys0, n, W.cells);
 
     PermSet S{};
     uint64_t* fields[] = {(uint64_t*)p->x, (uint64_t*)p->y, (uint64_t*)p->z,
@@ -421,7 +441,14 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
     for (uint64_t* f : fields)
         if (f) S.f[S.nf++] = f;
     k_gather<<<grid_xcd(nb), kBlock, 0, s>>>(S, W.idx0, (uint64_t*)W.tmp, n);
-    k_scatter_back<<<nb, kBlock, 0, s>>>(S, (const uint64_t*)W.tmp, n);
+    k_scatter_back<<<nb, kBlock, 0, s>>>(S, (const uint64_t*)W.tmp, n, W.p4);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_p4(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    k_pack_p4<<<nb, kBlock, 0, s>>>(p->x, p->y, p->z, p->h, P.n, W.p4);
     return hipGetLastError();
 }
 

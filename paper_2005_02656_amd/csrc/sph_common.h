@@ -3,9 +3,9 @@
 // Data layout in HBM (all caller-owned, see include/sph.h):
 //   * particle fields are structure-of-arrays FP64, one array per field, so a
 //     wavefront of 64 consecutive slots reads 512 contiguous bytes per field;
-//   * neighbour lists are int32 in column-major (ELL) layout, entry j of slot a
-//     at list[j*stride + a], so the 64 lanes of a wavefront reading entry j of
-//     their own targets hit 256 contiguous bytes;
+//   * neighbour lists are int32 in tiles of 64 slots (see lpos), so the 64 lanes
+//     of a wavefront reading entry j of their own targets hit 256 contiguous
+//     bytes and one wavefront's rows are contiguous;
 //   * the workspace holds the device-resident domain record, sort buffers, the
 //     dense cell table (start/end/max-h per Morton cell) and the lists.
 #pragma once
@@ -27,7 +27,6 @@ constexpr int kMaxPermFields = 16;
 // POD copied by value into every kernel.
 struct Params {
     int64_t n;
-    int64_t stride;        // list column stride (= n)
     double box_lo[3], box_hi[3], L[3], halfL[3];
     int periodic[3];
     int sinc_n;
@@ -41,6 +40,7 @@ struct Params {
     double courant, growth, acc_dt, energy_dt;
     int lcap;              // largest admissible cell level (8^lcap <= table size)
     int precision;
+    int cand_cap;          // candidate-list capacity of the fused step (0: off)
 };
 
 // ---------------------------------------------------------------- device domain
@@ -61,13 +61,47 @@ struct Domain {
     int64_t built_n;
 };
 
+// ---------------------------------------------------------------- packed records
+// Gathered per neighbour; one record is a few 16-byte loads instead of one
+// load per structure-of-arrays field.
+struct alignas(32) Pos4 {
+    double x, y, z, h;
+};
+// what the momentum/energy pass needs of a neighbour besides its position
+struct alignas(16) MomRec {
+    double c11, c12, c13, c22, c23, c33;   // IAD matrix C = tau^-1
+    double irho, c, pb, m;                 // 1/rho, sound speed, P/(Omega rho^2), mass
+    double vx, vy, vz, invh, pad0, pad1;
+};
+struct alignas(16) CellRange {
+    int32_t s, e;   // particle slots [s, e) of one Morton cell
+    double hmax;    // largest h in the cell (set before the symmetric searches)
+};
+
+// ---------------------------------------------------------------- neighbour lists
+// Lists are stored in tiles of 64 consecutive slots (one wavefront): entry j of
+// slot a lives at ((a/64)*cap + j)*64 + a%64.  Lanes reading or writing entry j
+// of their own targets touch one 256-byte row, and one wavefront's rows are
+// contiguous (a global column-major layout would put them n*4 bytes apart).
+__host__ __device__ inline int64_t lpos(int64_t a, int j, int cap)
+{
+    return ((a >> 6) * (int64_t)cap + j) * 64 + (a & 63);
+}
+
+// The fused step walks the cells once for a candidate list with reach
+// 2 kappa max(h0_a, h0_b): the Newton clamp keeps h <= kappa h0, so every set
+// the step needs is a subset.  Used when kappa <= kFusedKappaMax; the
+// workspace layout depends on (n, ng_max) only, never on per-call parameters.
+constexpr double kFusedKappaMax = 1.25;
+int candidate_capacity(int ng_max);
+
 // ---------------------------------------------------------------- workspace layout
 struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
-    size_t cstart, cend, chmax, nc, ns, list;
+    size_t cells, nc, ns, nk, p4, rec, vol, list, cand, posm, mf, mf2;
     size_t total;
     int64_t n, nsort_blocks, hist_len, scan_blocks, ncells_cap;
-    int lcap;
+    int lcap, cand_cap;
 };
 Layout make_layout(int64_t n, int ng_max);
 
@@ -79,9 +113,15 @@ struct Ws {
     uint32_t *idx0, *idx1;
     uint32_t* hist;
     uint32_t* scanpart;
-    int32_t *cstart, *cend;
-    double* chmax;
+    CellRange* cells;
     int32_t *nc, *ns, *list;
+    int32_t *nk, *cand;        // candidate counts and lists of the fused step
+    Pos4* p4;
+    MomRec* rec;
+    double* vol;               // m/rho per particle (IAD pass)
+    void* posm;                // mixed precision: cell index + FP32 offsets (16 B)
+    void* recm;                // mixed precision: FP32 momentum records (aliases rec)
+    float *mf, *mf2;           // mixed precision: FP32 mass and volume
     double* tmp;               // permute scratch (aliases the list area)
 };
 Ws carve(void* ws, const Layout& L);
@@ -176,6 +216,20 @@ constexpr SincTable kSinc{};
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kPiHalfSq = (kPi * kPi) / 4.0;
 
+// s^(n-1) for the integer exponent n (n is uniform across the launch; the usual
+// n = 6 takes three multiplications)
+template <class T>
+SPH_DEV T pow_nm1(T s, int n)
+{
+    if (n == 6) {
+        T s2 = s * s;
+        return s2 * s2 * s;
+    }
+    T p = T(1);
+    for (int i = 1; i < n; ++i) p = p * s;
+    return p;
+}
+
 // S_n and v dS_n/dv at t = (pi/2)^2 v^2, integer n >= 1
 SPH_DEV void sinc_terms(double t, int n, double& S, double& vdS)
 {
@@ -186,8 +240,7 @@ SPH_DEV void sinc_terms(double t, int n, double& S, double& vdS)
 #pragma unroll
     for (int k = kSincTerms - 3; k >= 0; --k) q = fma(q, t, kSinc.d[k]);
     q = q * t;                      // x sinc'(x)
-    double p = 1.0;                 // s^(n-1)
-    for (int i = 1; i < n; ++i) p = p * s;
+    const double p = pow_nm1(s, n); // s^(n-1)
     S = p * s;
     vdS = (double)n * p * q;
 }
@@ -197,10 +250,15 @@ SPH_DEV double sinc_S(double t, int n)
     double s = kSinc.s[kSincTerms - 1];
 #pragma unroll
     for (int k = kSincTerms - 2; k >= 0; --k) s = fma(s, t, kSinc.s[k]);
-    double p = s;
-    for (int i = 1; i < n; ++i) p = p * s;
-    return p;
+    return pow_nm1(s, n) * s;
 }
+
+// neighbour loops load this many neighbours' records before computing on them
+// (independent gathers in flight per wavefront)
+#ifndef SPH_GATHER_BATCH
+#define SPH_GATHER_BATCH 8
+#endif
+constexpr int kBatch = SPH_GATHER_BATCH;
 
 // ------------------------------------------------------------- launch helpers
 // The hardware hands workgroup i to XCD (i mod 8); remap so that each XCD
@@ -217,21 +275,36 @@ SPH_DEV int64_t xcd_block(int64_t nb)
 }
 
 // ------------------------------------------------------------- host launchers
-Params make_params(const sph_config* cfg, double bn, int lcap);
+Params make_params(const sph_config* cfg, double bn, int lcap, int cand_cap);   // cand_cap 0: fused path off
 double sinc_bn(int n);   // host: B_n normalisation
 
 hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
                               const sph_particles* p, hipStream_t s);
+// `pack` refreshes the packed positions from the caller's x, y, z, h first (the
+// stage entry points do; sph_step packs once after the cell build)
+hipError_t launch_pack_p4(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s);
 hipError_t launch_update_h(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                           hipStream_t s);
+                           hipStream_t s, bool pack);
 hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
                                  const sph_particles* p, hipStream_t s);
 hipError_t launch_density(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                          hipStream_t s);
+                          hipStream_t s, bool pack);
+// write_rec: also fill the momentum records (sph_step), else momentum packs them
 hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                      hipStream_t s);
+                      hipStream_t s, bool pack, bool write_rec);
 hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
-                                  sph_particles* p, hipStream_t s);
+                                  sph_particles* p, hipStream_t s, bool pack);
+// mixed-precision forms of the three pair passes (precision SPH_MIXED)
+size_t mixed_posm_bytes();
+size_t mixed_rec_bytes();
+hipError_t launch_density_mixed(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                                hipStream_t s, bool pack);
+hipError_t launch_iad_mixed(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                            hipStream_t s, bool pack, bool write_rec);
+hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const Ws& W,
+                                        sph_particles* p, hipStream_t s, bool pack);
+hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                                hipStream_t s);
 hipError_t launch_timestep(const Params& P, const Ws& W, sph_globals* g, hipStream_t s);
 hipError_t launch_integrate(const Params& P, const Ws& W, sph_particles* p, sph_globals* g,
                             hipStream_t s);

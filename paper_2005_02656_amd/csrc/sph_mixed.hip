@@ -1,0 +1,436 @@
+// sph_mixed.hip -- mixed-precision pair passes (precision SPH_MIXED).
+//
+// The paper keeps FP64 throughout and names a mixed-precision approach as
+// future work (section 4.2).  This form evaluates every pair term of the
+// density, IAD and momentum/energy passes in FP32 and accumulates the
+// per-particle sums in FP64.  Positions are an FP64 cell origin (the cell of
+// the last build, recovered from a packed integer cell index) plus an FP32
+// offset, so a pair displacement is (cell difference x cell edge) + (offset
+// difference) in FP32 with the minimum image taken on cell indices.  The
+// neighbour test that builds the lists, the Newton update of h, the EOS, the
+// 3x3 inversion, the integrator and the global sums stay in FP64.
+//
+// Gathered bytes per neighbour: 16 (position) + 4 (mass or volume) in the
+// density and IAD passes, 16 + 64 in the momentum pass (FP64: 32 + 8, 32 + 128).
+#include "sph_common.h"
+
+namespace sph {
+namespace {
+
+constexpr int kSincTermsF = 10;   // FP32: pi^20/21! < 2e-10
+
+struct alignas(16) PosM {
+    float ox, oy, oz;     // offset from the cell origin
+    uint32_t cpack;       // cell coordinates, 10 bits per axis (x | y << 10 | z << 20)
+};
+struct alignas(16) RecM {
+    float c11, c12, c13, c22, c23, c33;
+    float irho, c, pb, m;
+    float vx, vy, vz, invh;
+    float pad0, pad1;
+};
+
+struct CellGeom {
+    float ce[3];          // cell edges
+    int nax;
+    int periodic[3];
+};
+
+__device__ __forceinline__ CellGeom cell_geom(const Params& P, const Domain& D)
+{
+    CellGeom g;
+    for (int k = 0; k < 3; ++k) {
+        g.ce[k] = (float)D.cell[k];
+        g.periodic[k] = P.periodic[k];
+    }
+    g.nax = D.ncell_axis;
+    return g;
+}
+
+__device__ __forceinline__ float axis_disp(int ca, int cb, float oa, float ob, float ce, bool per,
+                                           int nax)
+{
+    int dc = cb - ca;
+    if (per) {
+        if (dc > nax / 2) dc -= nax;
+        else if (dc < -(nax / 2)) dc += nax;
+    }
+    return (float)dc * ce + (ob - oa);
+}
+
+// displacement b - a and its square, all FP32
+__device__ __forceinline__ float disp_m(const CellGeom& g, const PosM& a, const PosM& b, float& dx,
+                                        float& dy, float& dz)
+{
+    dx = axis_disp(a.cpack & 1023u, b.cpack & 1023u, a.ox, b.ox, g.ce[0], g.periodic[0], g.nax);
+    dy = axis_disp((a.cpack >> 10) & 1023u, (b.cpack >> 10) & 1023u, a.oy, b.oy, g.ce[1],
+                   g.periodic[1], g.nax);
+    dz = axis_disp(a.cpack >> 20, b.cpack >> 20, a.oz, b.oz, g.ce[2], g.periodic[2], g.nax);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ void sinc_terms_f(float t, int n, float& S, float& vdS)
+{
+    float s = (float)kSinc.s[kSincTermsF - 1];
+#pragma unroll
+    for (int k = kSincTermsF - 2; k >= 0; --k) s = fmaf(s, t, (float)kSinc.s[k]);
+    float q = (float)kSinc.d[kSincTermsF - 2];
+#pragma unroll
+    for (int k = kSincTermsF - 3; k >= 0; --k) q = fmaf(q, t, (float)kSinc.d[k]);
+    q = q * t;
+    float p = 1.0f;
+    for (int i = 1; i < n; ++i) p = p * s;
+    S = p * s;
+    vdS = (float)n * p * q;
+}
+
+__device__ __forceinline__ float sinc_S_f(float t, int n)
+{
+    float s = (float)kSinc.s[kSincTermsF - 1];
+#pragma unroll
+    for (int k = kSincTermsF - 2; k >= 0; --k) s = fmaf(s, t, (float)kSinc.s[k]);
+    float p = s;
+    for (int i = 1; i < n; ++i) p = p * s;
+    return p;
+}
+
+// positions as cell index + FP32 offset, and FP32 masses
+__global__ __launch_bounds__(kBlock) void k_pack_posm(Params P, const Domain* __restrict__ dom,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ m,
+                                                      PosM* __restrict__ pm,
+                                                      float* __restrict__ mf)
+{
+    int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= P.n) return;
+    const Domain D = *dom;
+    const int sh = kKeyBits - D.level;
+    const double pos[3] = {x[i], y[i], z[i]};
+    uint32_t c[3];
+    float o[3];
+    for (int k = 0; k < 3; ++k) {
+        c[k] = quantize(pos[k], D.lo[k], D.scale[k]) >> sh;
+        o[k] = (float)((pos[k] - D.lo[k]) - (double)c[k] * D.cell[k]);
+    }
+    pm[i] = PosM{o[0], o[1], o[2], c[0] | (c[1] << 10) | (c[2] << 20)};
+    mf[i] = (float)m[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_density_m(Params P, Domain* __restrict__ dom,
+                                                      const int32_t* __restrict__ nc,
+                                                      const int32_t* __restrict__ list,
+                                                      const PosM* __restrict__ pm,
+                                                      const float* __restrict__ mf,
+                                                      const double* __restrict__ h,
+                                                      const double* __restrict__ m,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ p_ref,
+                                                      const double* __restrict__ rho_ref,
+                                                      double* __restrict__ rho,
+                                                      double* __restrict__ omega,
+                                                      double* __restrict__ pr,
+                                                      double* __restrict__ cs)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    if (a >= P.n) return;
+    const CellGeom g = cell_geom(P, *dom);
+    const PosM pa = pm[a];
+    const double ha = h[a];
+    const float tsc = (float)(kPiHalfSq / (ha * ha));
+    const int cnt = min(nc[a], P.ng_max);
+    double sS = m[a], sD = 3.0 * m[a];
+#pragma unroll 2
+    for (int j = 0; j < cnt; ++j) {
+        int32_t b = list[lpos(a, j, P.ng_max)];
+        if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
+        float dx, dy, dz;
+        float r2 = disp_m(g, pa, pm[b], dx, dy, dz);
+        float S, vdS;
+        sinc_terms_f(r2 * tsc, P.sinc_n, S, vdS);
+        const float mb = mf[b];
+        sS += (double)(mb * S);
+        sD += (double)(mb * (3.0f * S + vdS));
+    }
+    const double w0 = P.bn / (ha * ha * ha);
+    const double r = w0 * sS;
+    const double om = 1.0 - w0 * sD / (3.0 * r);
+    double p, c;
+    if (P.eos == SPH_EOS_IDEAL) {
+        p = (P.gamma - 1.0) * r * u[a];
+        c = sqrt(P.gamma * (P.gamma - 1.0) * u[a]);
+    } else {
+        p = p_ref[a] + P.c0 * P.c0 * (r - rho_ref[a]);
+        c = P.c0;
+    }
+    rho[a] = r;
+    omega[a] = om;
+    pr[a] = p;
+    cs[a] = c;
+    if (!isfinite(r) || !isfinite(om) || !isfinite(p) || !isfinite(c))
+        set_err(dom, SPH_ERRBIT_NONFINITE);
+}
+
+__global__ __launch_bounds__(kBlock) void k_volume_m(int64_t n, const double* __restrict__ m,
+                                                     const double* __restrict__ rho,
+                                                     float* __restrict__ vol)
+{
+    int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i < n) vol[i] = (float)(m[i] / rho[i]);
+}
+
+struct RecSrcM {
+    const double *m, *rho, *omega, *p, *c, *vx, *vy, *vz, *h;
+};
+
+__device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, double c11, double c12,
+                                          double c13, double c22, double c23, double c33)
+{
+    RecM q;
+    q.c11 = (float)c11; q.c12 = (float)c12; q.c13 = (float)c13;
+    q.c22 = (float)c22; q.c23 = (float)c23; q.c33 = (float)c33;
+    const double r = R.rho[a];
+    q.irho = (float)(1.0 / r);
+    q.c = (float)R.c[a];
+    q.pb = (float)(R.p[a] / (R.omega[a] * r * r));
+    q.m = (float)R.m[a];
+    q.vx = (float)R.vx[a]; q.vy = (float)R.vy[a]; q.vz = (float)R.vz[a];
+    q.invh = (float)(1.0 / R.h[a]);
+    q.pad0 = 0.0f; q.pad1 = 0.0f;
+    return q;
+}
+
+__global__ __launch_bounds__(kBlock) void k_iad_m(Params P, Domain* __restrict__ dom,
+                                                  const int32_t* __restrict__ nc,
+                                                  const int32_t* __restrict__ list,
+                                                  const PosM* __restrict__ pm,
+                                                  const float* __restrict__ vol,
+                                                  const double* __restrict__ h,
+                                                  double* __restrict__ c11, double* __restrict__ c12,
+                                                  double* __restrict__ c13, double* __restrict__ c22,
+                                                  double* __restrict__ c23, double* __restrict__ c33,
+                                                  RecSrcM R, RecM* __restrict__ rec)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    if (a >= P.n) return;
+    const CellGeom g = cell_geom(P, *dom);
+    const PosM pa = pm[a];
+    const double ha = h[a];
+    const float tsc = (float)(kPiHalfSq / (ha * ha));
+    const float w0 = (float)(P.bn / (ha * ha * ha));
+    const int cnt = min(nc[a], P.ng_max);
+    double t11 = 0, t12 = 0, t13 = 0, t22 = 0, t23 = 0, t33 = 0;
+#pragma unroll 2
+    for (int j = 0; j < cnt; ++j) {
+        int32_t b = list[lpos(a, j, P.ng_max)];
+        if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
+        float dx, dy, dz;
+        float r2 = disp_m(g, pa, pm[b], dx, dy, dz);
+        const float s = vol[b] * (w0 * sinc_S_f(r2 * tsc, P.sinc_n));
+        const float sx = s * dx, sy = s * dy, sz = s * dz;
+        t11 += (double)(sx * dx);
+        t12 += (double)(sx * dy);
+        t13 += (double)(sx * dz);
+        t22 += (double)(sy * dy);
+        t23 += (double)(sy * dz);
+        t33 += (double)(sz * dz);
+    }
+    // 3x3 inversion in FP64
+    double a11 = t22 * t33 - t23 * t23;
+    double a12 = t13 * t23 - t12 * t33;
+    double a13 = t12 * t23 - t13 * t22;
+    double a22 = t11 * t33 - t13 * t13;
+    double a23 = t12 * t13 - t11 * t23;
+    double a33 = t11 * t22 - t12 * t12;
+    double det = t11 * a11 + t12 * a12 + t13 * a13;
+    if (det > 0.0) {
+        double id = 1.0 / det;
+        a11 *= id; a12 *= id; a13 *= id; a22 *= id; a23 *= id; a33 *= id;
+    } else {
+        a11 = a12 = a13 = a22 = a23 = a33 = 0.0;
+        set_err(dom, SPH_ERRBIT_SINGULAR_TAU);
+    }
+    c11[a] = a11; c12[a] = a12; c13[a] = a13;
+    c22[a] = a22; c23[a] = a23; c33[a] = a33;
+    if (rec) rec[a] = make_recm(R, a, a11, a12, a13, a22, a23, a33);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_recm(int64_t n, RecSrcM R,
+                                                      const double* __restrict__ c11,
+                                                      const double* __restrict__ c12,
+                                                      const double* __restrict__ c13,
+                                                      const double* __restrict__ c22,
+                                                      const double* __restrict__ c23,
+                                                      const double* __restrict__ c33,
+                                                      RecM* __restrict__ rec)
+{
+    int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (a < n) rec[a] = make_recm(R, a, c11[a], c12[a], c13[a], c22[a], c23[a], c33[a]);
+}
+
+struct MomOutM {
+    double *ax, *ay, *az, *du;
+};
+
+__global__ void k_dtmin_begin_m(Domain* d) { d->dtmin_bits = ord_bits(INFINITY); }
+
+__global__ __launch_bounds__(kBlock) void k_momentum_energy_m(Params P, Domain* __restrict__ dom,
+                                                              const int32_t* __restrict__ nc,
+                                                              const int32_t* __restrict__ ns,
+                                                              const int32_t* __restrict__ list,
+                                                              const PosM* __restrict__ pm,
+                                                              const RecM* __restrict__ rec,
+                                                              const double* __restrict__ h,
+                                                              const double* __restrict__ cdbl,
+                                                              const double* __restrict__ u,
+                                                              MomOutM O)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    double dtc = INFINITY;
+    if (a < P.n) {
+        const CellGeom g = cell_geom(P, *dom);
+        const PosM pa = pm[a];
+        const RecM ra = rec[a];
+        const double ha = h[a];
+        const float tsa = (float)(kPiHalfSq / (ha * ha));
+        const float w0a = (float)(P.bn / (ha * ha * ha));
+        const float bn = (float)P.bn;
+        const float al = (float)P.alpha;
+        const float pa_ = ra.pb, ira = ra.irho, ca = ra.c;
+        const int ng = P.ng_max;
+        const int cg = min(nc[a], ng);
+        const int co = min(ns[a] - nc[a], ng);
+        double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
+        const int total = cg + co;
+#pragma unroll 2
+        for (int k = 0; k < total; ++k) {
+            const bool gather = k < cg;
+            const int j = gather ? k : ng - 1 - (k - cg);
+            const int32_t b = list[lpos(a, j, ng)];
+            if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
+            const RecM rb = rec[b];
+            float dx, dy, dz;
+            const float r2 = disp_m(g, pa, pm[b], dx, dy, dz);
+            float Wa = 0.0f;
+            if (gather) Wa = w0a * sinc_S_f(r2 * tsa, P.sinc_n);
+            // support of W(h_b): v_b < 2, i.e. t_b < pi^2
+            const float ih2 = rb.invh * rb.invh;
+            const float tb = r2 * ((float)kPiHalfSq * ih2);
+            float Wb = 0.0f;
+            if (tb < (float)(4.0 * kPiHalfSq)) Wb = bn * (ih2 * rb.invh) * sinc_S_f(tb, P.sinc_n);
+            const float Aax = (ra.c11 * dx + ra.c12 * dy + ra.c13 * dz) * Wa;
+            const float Aay = (ra.c12 * dx + ra.c22 * dy + ra.c23 * dz) * Wa;
+            const float Aaz = (ra.c13 * dx + ra.c23 * dy + ra.c33 * dz) * Wa;
+            const float Abx = (rb.c11 * dx + rb.c12 * dy + rb.c13 * dz) * Wb;
+            const float Aby = (rb.c12 * dx + rb.c22 * dy + rb.c23 * dz) * Wb;
+            const float Abz = (rb.c13 * dx + rb.c23 * dy + rb.c33 * dz) * Wb;
+            const float vx = ra.vx - rb.vx, vy = ra.vy - rb.vy, vz = ra.vz - rb.vz;
+            const float xv = -(vx * dx + vy * dy + vz * dz);
+            float Pi = 0.0f;
+            if (xv < 0.0f) {
+                const float w = xv * rsqrtf(r2);
+                const float vsig = ca + rb.c - 3.0f * w;
+                Pi = -0.5f * al * vsig * w;
+            }
+            const float mb = rb.m;
+            const float gk = 0.5f * mb * Pi;
+            const float gx = gk * (Aax * ira + Abx * rb.irho);
+            const float gy = gk * (Aay * ira + Aby * rb.irho);
+            const float gz = gk * (Aaz * ira + Abz * rb.irho);
+            axs += (double)(-(mb * (pa_ * Aax + rb.pb * Abx)) - gx);
+            ays += (double)(-(mb * (pa_ * Aay + rb.pb * Aby)) - gy);
+            azs += (double)(-(mb * (pa_ * Aaz + rb.pb * Abz)) - gz);
+            e1 += (double)(mb * (vx * Aax + vy * Aay + vz * Aaz));
+            e2 += (double)(vx * gx + vy * gy + vz * gz);
+        }
+        // the energy rate is assembled in FP64
+        const double du = (double)pa_ * e1 + 0.5 * e2;
+        O.ax[a] = axs;
+        O.ay[a] = ays;
+        O.az[a] = azs;
+        O.du[a] = du;
+        if (!isfinite(axs) || !isfinite(ays) || !isfinite(azs) || !isfinite(du))
+            set_err(dom, SPH_ERRBIT_NONFINITE);
+        const double cA = cdbl[a];
+        dtc = P.courant * (ha / cA);
+        if (P.acc_dt > 0.0) {
+            double am = sqrt((axs * axs + ays * ays) + azs * azs);
+            double qa = P.acc_dt * sqrt(ha / am);
+            if (qa < dtc) dtc = qa;
+        }
+        if (P.energy_dt > 0.0) {
+            double qu = P.energy_dt * (fabs(u[a]) / fabs(du));
+            if (qu < dtc) dtc = qu;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, o, 64));
+    if ((threadIdx.x & 63) == 0 && dtc < INFINITY)
+        atomicMin((unsigned long long*)&dom->dtmin_bits, (unsigned long long)ord_bits(dtc));
+}
+
+RecSrcM recm_src(const sph_particles* p)
+{
+    return RecSrcM{p->m, p->rho, p->omega, p->p, p->c, p->vx, p->vy, p->vz, p->h};
+}
+
+}  // namespace
+
+static_assert(sizeof(PosM) == 16, "PosM layout");
+static_assert(sizeof(RecM) == 64, "RecM layout");
+size_t mixed_posm_bytes() { return sizeof(PosM); }
+size_t mixed_rec_bytes() { return sizeof(RecM); }
+
+hipError_t launch_density_mixed(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                                hipStream_t s, bool pack)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    PosM* pm = (PosM*)W.posm;
+    if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
+    k_density_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, pm, W.mf, p->h, p->m,
+                                                p->u, p->p_ref, p->rho_ref, p->rho, p->omega,
+                                                p->p, p->c);
+    return hipGetLastError();
+}
+
+hipError_t launch_iad_mixed(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                            hipStream_t s, bool pack, bool write_rec)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    PosM* pm = (PosM*)W.posm;
+    if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
+    k_volume_m<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.mf2);
+    k_iad_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, pm, W.mf2, p->h, p->c11,
+                                            p->c12, p->c13, p->c22, p->c23, p->c33, recm_src(p),
+                                            write_rec ? (RecM*)W.recm : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const Ws& W,
+                                        sph_particles* p, hipStream_t s, bool pack)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    PosM* pm = (PosM*)W.posm;
+    RecM* rec = (RecM*)W.recm;
+    if (pack) {
+        k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
+        k_pack_recm<<<nb, kBlock, 0, s>>>(P.n, recm_src(p), p->c11, p->c12, p->c13, p->c22,
+                                          p->c23, p->c33, rec);
+    }
+    MomOutM O{p->ax, p->ay, p->az, p->du};
+    k_dtmin_begin_m<<<1, 1, 0, s>>>(W.dom);
+    k_momentum_energy_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, pm, rec,
+                                                        p->h, p->c, p->u, O);
+    return hipGetLastError();
+}
+
+}  // namespace sph

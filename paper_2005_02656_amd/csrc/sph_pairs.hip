@@ -4,9 +4,10 @@
 // minimum time step (section 4.2).
 //
 // One thread per target slot, wavefronts mapped XCD-contiguously; list column j
-// of 64 consecutive targets is one 256-byte coalesced load; neighbour fields
-// are gathers from Morton-local slots (L1/L2 resident).  Sums are in FP64 in
-// list order; no atomics on floating point values.
+// of 64 consecutive targets is one 256-byte coalesced load.  Neighbour data is
+// gathered as packed records (32-byte positions, 128-byte momentum records) from
+// Morton-local slots (L1/L2 resident).  Sums are FP64 in list order; no atomics
+// on floating-point values.
 #include "sph_common.h"
 
 namespace sph {
@@ -15,10 +16,7 @@ namespace {
 __global__ __launch_bounds__(kBlock) void k_density(Params P, Domain* __restrict__ dom,
                                                     const int32_t* __restrict__ nc,
                                                     const int32_t* __restrict__ list,
-                                                    const double* __restrict__ x,
-                                                    const double* __restrict__ y,
-                                                    const double* __restrict__ z,
-                                                    const double* __restrict__ h,
+                                                    const Pos4* __restrict__ p4,
                                                     const double* __restrict__ m,
                                                     const double* __restrict__ u,
                                                     const double* __restrict__ p_ref,
@@ -33,21 +31,38 @@ __global__ __launch_bounds__(kBlock) void k_density(Params P, Domain* __restrict
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
     if (a >= P.n) return;
-    const double xa = x[a], ya = y[a], za = z[a], ha = h[a];
+    const Pos4 pa = p4[a];
+    const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
     const double tsc = kPiHalfSq / (ha * ha);
     const int cnt = min(nc[a], P.ng_max);
     // self term: S = 1, v dS/dv = 0
     double sS = m[a], sD = 3.0 * m[a];
-    for (int j = 0; j < cnt; ++j) {
-        int32_t b = list[(int64_t)j * P.stride + a];
-        if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;  // lists not built for this ws
-        double dx, dy, dz;
-        double r2 = disp(P, xa, ya, za, x[b], y[b], z[b], dx, dy, dz);
-        double S, vdS;
-        sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
-        double mb = m[b];
-        sS += mb * S;
-        sD += mb * (3.0 * S + vdS);
+    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+        int32_t bb[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            int32_t b = (j0 + u < cnt) ? list[lpos(a, j0 + u, P.ng_max)] : -1;
+            ok[u] = (uint32_t)b < (uint32_t)P.n;   // also rejects lists not built for this ws
+            bb[u] = ok[u] ? b : (int32_t)a;
+        }
+        double qx[kBatch], qy[kBatch], qz[kBatch], mb[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const Pos4* q = p4 + bb[u];
+            qx[u] = q->x; qy[u] = q->y; qz[u] = q->z;
+            mb[u] = m[bb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (!ok[u]) continue;
+            double dx, dy, dz;
+            double r2 = disp(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
+            double S, vdS;
+            sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
+            sS += mb[u] * S;
+            sD += mb[u] * (3.0 * S + vdS);
+        }
     }
     const double w0 = P.bn / (ha * ha * ha);
     const double r = w0 * sS;
@@ -69,41 +84,85 @@ __global__ __launch_bounds__(kBlock) void k_density(Params P, Domain* __restrict
         set_err(dom, SPH_ERRBIT_NONFINITE);
 }
 
+// volume m/rho of every particle (one division per particle instead of per pair)
+__global__ __launch_bounds__(kBlock) void k_volume(int64_t n, const double* __restrict__ m,
+                                                   const double* __restrict__ rho,
+                                                   double* __restrict__ vol)
+{
+    int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i < n) vol[i] = m[i] / rho[i];
+}
+
+struct RecSrc {
+    const double *m, *rho, *omega, *p, *c, *vx, *vy, *vz, *h;
+};
+
+__device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, double c11, double c12,
+                                           double c13, double c22, double c23, double c33)
+{
+    MomRec q;
+    q.c11 = c11; q.c12 = c12; q.c13 = c13; q.c22 = c22; q.c23 = c23; q.c33 = c33;
+    const double r = R.rho[a];
+    q.irho = 1.0 / r;
+    q.c = R.c[a];
+    q.pb = R.p[a] / (R.omega[a] * r * r);
+    q.m = R.m[a];
+    q.vx = R.vx[a]; q.vy = R.vy[a]; q.vz = R.vz[a];
+    q.invh = 1.0 / R.h[a];
+    q.pad0 = 0.0; q.pad1 = 0.0;
+    return q;
+}
+
 __global__ __launch_bounds__(kBlock) void k_iad(Params P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ list,
-                                                const double* __restrict__ x,
-                                                const double* __restrict__ y,
-                                                const double* __restrict__ z,
-                                                const double* __restrict__ h,
-                                                const double* __restrict__ m,
-                                                const double* __restrict__ rho,
+                                                const Pos4* __restrict__ p4,
+                                                const double* __restrict__ vol,
                                                 double* __restrict__ c11, double* __restrict__ c12,
                                                 double* __restrict__ c13, double* __restrict__ c22,
-                                                double* __restrict__ c23, double* __restrict__ c33)
+                                                double* __restrict__ c23, double* __restrict__ c33,
+                                                RecSrc R, MomRec* __restrict__ rec)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
     if (a >= P.n) return;
-    const double xa = x[a], ya = y[a], za = z[a], ha = h[a];
+    const Pos4 pa = p4[a];
+    const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
     const double tsc = kPiHalfSq / (ha * ha);
     const double w0 = P.bn / (ha * ha * ha);
     const int cnt = min(nc[a], P.ng_max);
     double t11 = 0, t12 = 0, t13 = 0, t22 = 0, t23 = 0, t33 = 0;
-    for (int j = 0; j < cnt; ++j) {
-        int32_t b = list[(int64_t)j * P.stride + a];
-        if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
-        double dx, dy, dz;
-        double r2 = disp(P, xa, ya, za, x[b], y[b], z[b], dx, dy, dz);
-        double s = m[b] / rho[b] * (w0 * sinc_S(r2 * tsc, P.sinc_n));
-        t11 += s * dx * dx;
-        t12 += s * dx * dy;
-        t13 += s * dx * dz;
-        t22 += s * dy * dy;
-        t23 += s * dy * dz;
-        t33 += s * dz * dz;
+    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+        int32_t bb[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            int32_t b = (j0 + u < cnt) ? list[lpos(a, j0 + u, P.ng_max)] : -1;
+            ok[u] = (uint32_t)b < (uint32_t)P.n;
+            bb[u] = ok[u] ? b : (int32_t)a;
+        }
+        double qx[kBatch], qy[kBatch], qz[kBatch], vb[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const Pos4* q = p4 + bb[u];
+            qx[u] = q->x; qy[u] = q->y; qz[u] = q->z;
+            vb[u] = vol[bb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (!ok[u]) continue;
+            double dx, dy, dz;
+            double r2 = disp(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
+            double s = vb[u] * (w0 * sinc_S(r2 * tsc, P.sinc_n));
+            t11 += s * dx * dx;
+            t12 += s * dx * dy;
+            t13 += s * dx * dz;
+            t22 += s * dy * dy;
+            t23 += s * dy * dz;
+            t33 += s * dz * dz;
+        }
     }
     double a11 = t22 * t33 - t23 * t23;
     double a12 = t13 * t23 - t12 * t33;
@@ -114,19 +173,29 @@ __global__ __launch_bounds__(kBlock) void k_iad(Params P, Domain* __restrict__ d
     double det = t11 * a11 + t12 * a12 + t13 * a13;
     if (det > 0.0) {
         double id = 1.0 / det;
-        c11[a] = a11 * id; c12[a] = a12 * id; c13[a] = a13 * id;
-        c22[a] = a22 * id; c23[a] = a23 * id; c33[a] = a33 * id;
+        a11 *= id; a12 *= id; a13 *= id; a22 *= id; a23 *= id; a33 *= id;
     } else {
-        c11[a] = 0.0; c12[a] = 0.0; c13[a] = 0.0;
-        c22[a] = 0.0; c23[a] = 0.0; c33[a] = 0.0;
+        a11 = a12 = a13 = a22 = a23 = a33 = 0.0;
         set_err(dom, SPH_ERRBIT_SINGULAR_TAU);
     }
+    c11[a] = a11; c12[a] = a12; c13[a] = a13;
+    c22[a] = a22; c23[a] = a23; c33[a] = a33;
+    if (rec) rec[a] = make_rec(R, a, a11, a12, a13, a22, a23, a33);
 }
 
-struct MomIn {
-    const double *x, *y, *z, *vx, *vy, *vz, *h, *m, *u, *rho, *omega, *p, *c;
-    const double *c11, *c12, *c13, *c22, *c23, *c33;
-};
+__global__ __launch_bounds__(kBlock) void k_pack_rec(int64_t n, RecSrc R,
+                                                     const double* __restrict__ c11,
+                                                     const double* __restrict__ c12,
+                                                     const double* __restrict__ c13,
+                                                     const double* __restrict__ c22,
+                                                     const double* __restrict__ c23,
+                                                     const double* __restrict__ c33,
+                                                     MomRec* __restrict__ rec)
+{
+    int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (a < n) rec[a] = make_rec(R, a, c11[a], c12[a], c13[a], c22[a], c23[a], c33[a]);
+}
+
 struct MomOut {
     double *ax, *ay, *az, *du;
 };
@@ -137,7 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_momentum_energy(Params P, Domain* __
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
                                                             const int32_t* __restrict__ list,
-                                                            MomIn I, MomOut O)
+                                                            const Pos4* __restrict__ p4,
+                                                            const MomRec* __restrict__ rec,
+                                                            const double* __restrict__ u,
+                                                            MomOut O)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
@@ -145,12 +217,11 @@ __global__ __launch_bounds__(kBlock) void k_momentum_energy(Params P, Domain* __
     const int64_t a = lb * kBlock + threadIdx.x;
     double dtc = INFINITY;
     if (a < P.n) {
-        const double xa = I.x[a], ya = I.y[a], za = I.z[a];
-        const double vxa = I.vx[a], vya = I.vy[a], vza = I.vz[a];
-        const double ha = I.h[a], ra = I.rho[a], ca = I.c[a];
-        const double C11 = I.c11[a], C12 = I.c12[a], C13 = I.c13[a];
-        const double C22 = I.c22[a], C23 = I.c23[a], C33 = I.c33[a];
-        const double pa = I.p[a] / (I.omega[a] * ra * ra);
+        const Pos4 pa = p4[a];
+        const MomRec ra = rec[a];
+        const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
+        const double vxa = ra.vx, vya = ra.vy, vza = ra.vz;
+        const double ca = ra.c, ira = ra.irho, pa_ = ra.pb;
         const double tsa = kPiHalfSq / (ha * ha);
         const double w0a = P.bn / (ha * ha * ha);
         const double al = P.alpha;
@@ -159,52 +230,71 @@ __global__ __launch_bounds__(kBlock) void k_momentum_energy(Params P, Domain* __
         const int co = min(ns[a] - nc[a], ng);
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
-        for (int k = 0; k < total; ++k) {
-            const bool gather = k < cg;
-            const int j = gather ? k : ng - 1 - (k - cg);
-            const int32_t b = list[(int64_t)j * P.stride + a];
-            if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
+        constexpr int kMomBatch = 2;
+        for (int k0 = 0; k0 < total; k0 += kMomBatch) {
+            int32_t bb[kMomBatch];
+            bool ok[kMomBatch], gat[kMomBatch];
+#pragma unroll
+            for (int u = 0; u < kMomBatch; ++u) {
+                const int k = k0 + u;
+                gat[u] = k < cg;
+                const int j = gat[u] ? k : ng - 1 - (k - cg);
+                int32_t b = (k < total) ? list[lpos(a, j, ng)] : -1;
+                ok[u] = (uint32_t)b < (uint32_t)P.n;
+                bb[u] = ok[u] ? b : (int32_t)a;
+            }
+            Pos4 qb[kMomBatch];
+            MomRec rbb[kMomBatch];
+#pragma unroll
+            for (int u = 0; u < kMomBatch; ++u) {
+                qb[u] = p4[bb[u]];
+                rbb[u] = rec[bb[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kMomBatch; ++u) {
+            if (!ok[u]) continue;
+            const bool gather = gat[u];
+            const Pos4& q = qb[u];
+            const MomRec& rb = rbb[u];
             double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, I.x[b], I.y[b], I.z[b], dx, dy, dz);
-            const double hb = I.h[b];
+            double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
             double Wa = 0.0;
             if (gather) Wa = w0a * sinc_S(r2 * tsa, P.sinc_n);
             double Wb = 0.0;
-            const double hb2 = 2.0 * hb;
-            if (r2 < hb2 * hb2) Wb = P.bn / (hb * hb * hb) * sinc_S(r2 * (kPiHalfSq / (hb * hb)), P.sinc_n);
+            const double hb2 = 2.0 * q.h;
+            if (r2 < hb2 * hb2) {
+                const double ih = rb.invh, ih2 = ih * ih;
+                Wb = P.bn * (ih2 * ih) * sinc_S(r2 * (kPiHalfSq * ih2), P.sinc_n);
+            }
             // A_ab(h_a) = C_a d W_a, A_ab(h_b) = C_b d W_b, d = x_b - x_a
-            const double Aax = (C11 * dx + C12 * dy + C13 * dz) * Wa;
-            const double Aay = (C12 * dx + C22 * dy + C23 * dz) * Wa;
-            const double Aaz = (C13 * dx + C23 * dy + C33 * dz) * Wa;
-            const double D11 = I.c11[b], D12 = I.c12[b], D13 = I.c13[b];
-            const double D22 = I.c22[b], D23 = I.c23[b], D33 = I.c33[b];
-            const double Abx = (D11 * dx + D12 * dy + D13 * dz) * Wb;
-            const double Aby = (D12 * dx + D22 * dy + D23 * dz) * Wb;
-            const double Abz = (D13 * dx + D23 * dy + D33 * dz) * Wb;
-            const double vx = vxa - I.vx[b], vy = vya - I.vy[b], vz = vza - I.vz[b];
+            const double Aax = (ra.c11 * dx + ra.c12 * dy + ra.c13 * dz) * Wa;
+            const double Aay = (ra.c12 * dx + ra.c22 * dy + ra.c23 * dz) * Wa;
+            const double Aaz = (ra.c13 * dx + ra.c23 * dy + ra.c33 * dz) * Wa;
+            const double Abx = (rb.c11 * dx + rb.c12 * dy + rb.c13 * dz) * Wb;
+            const double Aby = (rb.c12 * dx + rb.c22 * dy + rb.c23 * dz) * Wb;
+            const double Abz = (rb.c13 * dx + rb.c23 * dy + rb.c33 * dz) * Wb;
+            const double vx = vxa - rb.vx, vy = vya - rb.vy, vz = vza - rb.vz;
             // x_ab . v_ab with x_ab = -d
             const double xv = -(vx * dx + vy * dy + vz * dz);
-            const double rb = I.rho[b];
             double Pi = 0.0;
             if (xv < 0.0) {
                 const double w = xv / sqrt(r2);
-                const double vsig = ca + I.c[b] - 3.0 * w;
+                const double vsig = ca + rb.c - 3.0 * w;
                 Pi = -0.5 * al * vsig * w;
             }
-            const double mb = I.m[b];
-            const double pb = I.p[b] / (I.omega[b] * rb * rb);
+            const double mb = rb.m;
             const double gk = 0.5 * mb * Pi;
-            const double ira = 1.0 / ra, irb = 1.0 / rb;
-            const double gx = gk * (Aax * ira + Abx * irb);
-            const double gy = gk * (Aay * ira + Aby * irb);
-            const double gz = gk * (Aaz * ira + Abz * irb);
-            axs += -(mb * (pa * Aax + pb * Abx)) - gx;
-            ays += -(mb * (pa * Aay + pb * Aby)) - gy;
-            azs += -(mb * (pa * Aaz + pb * Abz)) - gz;
+            const double gx = gk * (Aax * ira + Abx * rb.irho);
+            const double gy = gk * (Aay * ira + Aby * rb.irho);
+            const double gz = gk * (Aaz * ira + Abz * rb.irho);
+            axs += -(mb * (pa_ * Aax + rb.pb * Abx)) - gx;
+            ays += -(mb * (pa_ * Aay + rb.pb * Aby)) - gy;
+            azs += -(mb * (pa_ * Aaz + rb.pb * Abz)) - gz;
             e1 += mb * (vx * Aax + vy * Aay + vz * Aaz);
             e2 += vx * gx + vy * gy + vz * gz;
+            }
         }
-        const double du = pa * e1 + 0.5 * e2;
+        const double du = pa_ * e1 + 0.5 * e2;
         O.ax[a] = axs;
         O.ay[a] = ays;
         O.az[a] = azs;
@@ -219,11 +309,11 @@ __global__ __launch_bounds__(kBlock) void k_momentum_energy(Params P, Domain* __
             if (qa < dtc) dtc = qa;
         }
         if (P.energy_dt > 0.0) {
-            double qu = P.energy_dt * (fabs(I.u[a]) / fabs(du));
+            double qu = P.energy_dt * (fabs(u[a]) / fabs(du));
             if (qu < dtc) dtc = qu;
         }
     }
-    // block minimum of the Courant candidates, one atomic per wavefront
+    // block minimum of the candidates, one atomic per wavefront
     for (int o = 32; o > 0; o >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, o, 64));
     if ((threadIdx.x & 63) == 0 && dtc < INFINITY)
         atomicMin((unsigned long long*)&dom->dtmin_bits, (unsigned long long)ord_bits(dtc));
@@ -240,36 +330,55 @@ __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals
     g->dt = dt;
 }
 
+RecSrc rec_src(const sph_particles* p)
+{
+    return RecSrc{p->m, p->rho, p->omega, p->p, p->c, p->vx, p->vy, p->vz, p->h};
+}
+
 }  // namespace
 
 hipError_t launch_density(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                          hipStream_t s)
+                          hipStream_t s, bool pack)
 {
+    if (pack) {
+        hipError_t e = launch_pack_p4(P, W, p, s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    k_density<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, p->x, p->y, p->z, p->h,
-                                              p->m, p->u, p->p_ref, p->rho_ref, p->rho, p->omega,
-                                              p->p, p->c);
+    k_density<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, p->m, p->u, p->p_ref,
+                                              p->rho_ref, p->rho, p->omega, p->p, p->c);
     return hipGetLastError();
 }
 
 hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                      hipStream_t s)
+                      hipStream_t s, bool pack, bool write_rec)
 {
+    if (pack) {
+        hipError_t e = launch_pack_p4(P, W, p, s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, p->x, p->y, p->z, p->h, p->m,
-                                          p->rho, p->c11, p->c12, p->c13, p->c22, p->c23, p->c33);
+    k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.vol);
+    k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, W.vol, p->c11, p->c12,
+                                          p->c13, p->c22, p->c23, p->c33, rec_src(p),
+                                          write_rec ? W.rec : nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
-                                  sph_particles* p, hipStream_t s)
+                                  sph_particles* p, hipStream_t s, bool pack)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    MomIn I{p->x, p->y, p->z, p->vx, p->vy, p->vz, p->h, p->m, p->u, p->rho, p->omega, p->p, p->c,
-            p->c11, p->c12, p->c13, p->c22, p->c23, p->c33};
+    if (pack) {
+        hipError_t e = launch_pack_p4(P, W, p, s);
+        if (e != hipSuccess) return e;
+        k_pack_rec<<<nb, kBlock, 0, s>>>(P.n, rec_src(p), p->c11, p->c12, p->c13, p->c22,
+                                         p->c23, p->c33, W.rec);
+    }
     MomOut O{p->ax, p->ay, p->az, p->du};
     k_dtmin_begin<<<1, 1, 0, s>>>(W.dom);
-    k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, I, O);
+    k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, W.p4, W.rec,
+                                                      p->u, O);
     return hipGetLastError();
 }
 

@@ -1,17 +1,38 @@
 // sph_search.hip -- smoothing-length Newton update and neighbour search.
 //
-// One thread per target slot; consecutive slots are Morton-consecutive, so the
-// 64 lanes of a wavefront sit in one or two cells and walk the same candidate
-// cells in lockstep: candidate positions are same-address loads across lanes
-// (one request per distinct cell) served from L1/L2.  Candidate cells are
-// culled by the distance from the target to the cell box, per axis, with a
-// margin that covers the rounding of the key quantisation.
+// Cell walk: one thread per target slot; consecutive slots are Morton-
+// consecutive, so the lanes of a wavefront sit in a few neighbouring cells and
+// walk mostly the same candidate cells (same-address loads across lanes, served
+// from L1/L2).  Cells are smaller than the kernel reach (edge >= h_max/2); each
+// target walks its own stencil and skips cells whose box is out of reach, with a
+// margin covering the rounding of the key quantisation.  Candidate positions and
+// h come from the packed 32-byte records.
+//
+// Two compositions use these kernels:
+//  * the stage entry points: Newton by cell walks (any kappa, any iteration
+//    count) and the neighbour lists by one more walk;
+//  * the fused step: ONE walk collects candidates within 2 kappa max(h0_a, h0_b)
+//    (a superset of every set the step needs, since the Newton clamp keeps
+//    h <= kappa h0), the Newton iterations sum over the candidate list, and a
+//    filter pass writes the exact lists from the candidates with the final h.
+//    The neighbour sets are identical; only the visiting order differs.
 #include "sph_common.h"
 
 namespace sph {
 namespace {
 
 constexpr double kCullMargin = 1e-9;  // relative to the cell edge
+
+// spread the low 10 bits of v to every third bit (cell coordinates, level <= 9)
+__device__ __forceinline__ uint32_t spread10(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
 
 struct AxisWalk {
     int lo, hi;      // offsets (or absolute cells when `all`)
@@ -67,23 +88,28 @@ __device__ __forceinline__ double axis_gap(const AxisWalk& a, int o)
     return d > 0.0 ? d : 0.0;
 }
 
-__device__ __forceinline__ int axis_cell(const AxisWalk& a, int o, int nax)
+__device__ __forceinline__ uint32_t axis_cell(const AxisWalk& a, int o, int nax)
 {
-    if (a.all || a.empty) return o;
+    if (a.all || a.empty) return (uint32_t)o;
     int c = a.c0 + o;
     if (c < 0) c += nax;
     else if (c >= nax) c -= nax;
-    return c;
+    return (uint32_t)c;
 }
 
 // Visit every particle of every cell whose box may hold a point closer than R
-// to `pos` and that `want(cell, gap2)` accepts.
+// to the target and that `want(cell, gap2)` accepts; body(b, record_of_b).
+// The cell records of one row (up to kRow cells along x) are loaded together,
+// then each cell's particle records in batches of four: independent loads in
+// flight instead of one dependent load per candidate.
 template <class Want, class Body>
 __device__ __forceinline__ void walk_cells(const Params& P, const Domain& D,
-                                           const int32_t* __restrict__ cs,
-                                           const int32_t* __restrict__ ce, double xa, double ya,
+                                           const CellRange* __restrict__ cells,
+                                           const Pos4* __restrict__ p4, double xa, double ya,
                                            double za, double R, Want&& want, Body&& body)
 {
+    constexpr int kRow = 8;
+    constexpr int kCellBatch = 4;
     const int nax = D.ncell_axis;
     AxisWalk wx = axis_walk(P, D, 0, xa, R);
     AxisWalk wy = axis_walk(P, D, 1, ya, R);
@@ -93,31 +119,68 @@ __device__ __forceinline__ void walk_cells(const Params& P, const Domain& D,
         double gz = axis_gap(wz, oz);
         double gz2 = gz * gz;
         if (gz2 >= R2) continue;
-        uint64_t mz = spread3((uint64_t)axis_cell(wz, oz, nax));
+        uint32_t mz = spread10(axis_cell(wz, oz, nax));
         for (int oy = wy.lo; oy <= wy.hi; ++oy) {
             double gy = axis_gap(wy, oy);
             double gzy2 = gz2 + gy * gy;
             if (gzy2 >= R2) continue;
-            uint64_t mzy = mz | (spread3((uint64_t)axis_cell(wy, oy, nax)) << 1);
-            for (int ox = wx.lo; ox <= wx.hi; ++ox) {
-                double gx = axis_gap(wx, ox);
-                double g2 = gzy2 + gx * gx;
-                if (g2 >= R2) continue;
-                uint64_t cid = mzy | (spread3((uint64_t)axis_cell(wx, ox, nax)) << 2);
-                if (!want(cid, g2)) continue;
-                int32_t b0 = cs[cid], b1 = ce[cid];
-                for (int32_t b = b0; b < b1; ++b) body(b);
+            uint32_t mzy = mz | (spread10(axis_cell(wy, oy, nax)) << 1);
+            for (int ox0 = wx.lo; ox0 <= wx.hi; ox0 += kRow) {
+                uint32_t cid[kRow];
+                double g2[kRow];
+                bool in[kRow];
+#pragma unroll
+                for (int i = 0; i < kRow; ++i) {
+                    const int ox = ox0 + i;
+                    double gx = (ox <= wx.hi) ? axis_gap(wx, ox) : 0.0;
+                    g2[i] = gzy2 + gx * gx;
+                    in[i] = (ox <= wx.hi) && g2[i] < R2;
+                    cid[i] = in[i] ? (mzy | (spread10(axis_cell(wx, ox, nax)) << 2)) : 0u;
+                }
+                CellRange cr[kRow];
+#pragma unroll
+                for (int i = 0; i < kRow; ++i) cr[i] = cells[cid[i]];
+#pragma unroll
+                for (int i = 0; i < kRow; ++i) {
+                    if (!in[i] || !want(cr[i], g2[i])) continue;
+                    const int32_t e = cr[i].e;
+                    for (int32_t b0 = cr[i].s; b0 < e; b0 += kCellBatch) {
+                        Pos4 q[kCellBatch];
+#pragma unroll
+                        for (int u = 0; u < kCellBatch; ++u) q[u] = p4[min(b0 + u, e - 1)];
+#pragma unroll
+                        for (int u = 0; u < kCellBatch; ++u)
+                            if (b0 + u < e) body(b0 + u, q[u]);
+                    }
+                }
             }
         }
     }
 }
 
+__device__ __forceinline__ double newton_step(const Params& P, double hc, double h0, double sS,
+                                              double sV)
+{
+    const double k3 = (32.0 * kPi / 3.0) * P.bn;
+    const double kap = P.kappa;
+    double F = k3 * sS - P.n_target;
+    double Fp = -(k3 / hc) * sV;
+    double hn = (Fp > 0.0) ? hc - F / Fp : kap * h0;
+    if (hn < h0 / kap) hn = h0 / kap;
+    if (hn > kap * h0) hn = kap * h0;
+    return hn;
+}
+
+__device__ __forceinline__ void check_cell_range(const Params& P, Domain* dom, double h)
+{
+    for (int k = 0; k < 3; ++k)
+        if (P.periodic[k] && !(4.0 * h < P.L[k])) set_err(dom, SPH_ERRBIT_CELL_RANGE);
+}
+
+// ---------------------------------------------------------------- cell-walk forms
 __global__ __launch_bounds__(kBlock) void k_update_h(Params P, const Domain* __restrict__ dom,
-                                                     const int32_t* __restrict__ cs,
-                                                     const int32_t* __restrict__ ce,
-                                                     const double* __restrict__ x,
-                                                     const double* __restrict__ y,
-                                                     const double* __restrict__ z,
+                                                     const CellRange* __restrict__ cells,
+                                                     const Pos4* __restrict__ p4,
                                                      double* __restrict__ h)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
@@ -126,20 +189,20 @@ __global__ __launch_bounds__(kBlock) void k_update_h(Params P, const Domain* __r
     const int64_t a = lb * kBlock + threadIdx.x;
     if (a >= P.n) return;
     const Domain D = *dom;
-    const double xa = x[a], ya = y[a], za = z[a];
+    const Pos4 pa = p4[a];
+    const double xa = pa.x, ya = pa.y, za = pa.z;
     const double h0 = h[a];
-    const double k3 = (32.0 * kPi / 3.0) * P.bn;
-    const double kap = P.kappa;
     double hc = h0;
     for (int it = 0; it < P.newton_iters; ++it) {
         const double h2 = 2.0 * hc;
         const double R2 = h2 * h2;
         const double tsc = kPiHalfSq / (hc * hc);
         double sS = 0.0, sV = 0.0;
-        walk_cells(P, D, cs, ce, xa, ya, za, h2, [](uint64_t, double) { return true; },
-                   [&](int32_t b) {
+        walk_cells(P, D, cells, p4, xa, ya, za, h2,
+                   [](const CellRange&, double) { return true; },
+                   [&](int32_t b, const Pos4& q) {
                        double dx, dy, dz;
-                       double r2 = disp(P, xa, ya, za, x[b], y[b], z[b], dx, dy, dz);
+                       double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
                        if (r2 < R2) {
                            double S, vdS;
                            sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
@@ -147,12 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_update_h(Params P, const Domain* __r
                            sV += vdS;
                        }
                    });
-        double F = k3 * sS - P.n_target;
-        double Fp = -(k3 / hc) * sV;
-        double hn = (Fp > 0.0) ? hc - F / Fp : kap * h0;
-        if (hn < h0 / kap) hn = h0 / kap;
-        if (hn > kap * h0) hn = kap * h0;
-        hc = hn;
+        hc = newton_step(P, hc, h0, sS, sV);
     }
     h[a] = hc;
 }
@@ -161,38 +219,29 @@ __global__ void k_hmax_begin(Domain* d) { d->hmax_new_bits = ord_bits(0.0); }
 
 // largest h per cell (for the symmetric search) and overall
 __global__ __launch_bounds__(kBlock) void k_cells_hmax(Params P, Domain* __restrict__ dom,
-                                                       const int32_t* __restrict__ cs,
-                                                       const int32_t* __restrict__ ce,
-                                                       const double* __restrict__ h,
-                                                       double* __restrict__ chmax, int64_t cap)
+                                                       CellRange* __restrict__ cells,
+                                                       const Pos4* __restrict__ p4, int64_t cap)
 {
     int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     int64_t ncell = int64_t(1) << (3 * dom->level);
     double hm = 0.0;
     if (c < ncell && c < cap) {
-        for (int32_t b = cs[c]; b < ce[c]; ++b) hm = fmax(hm, h[b]);
-        chmax[c] = hm;
+        const CellRange cr = cells[c];
+        for (int32_t b = cr.s; b < cr.e; ++b) hm = fmax(hm, p4[b].h);
+        cells[c].hmax = hm;
     }
     for (int o = 32; o > 0; o >>= 1) hm = fmax(hm, __shfl_xor(hm, o, 64));
     if ((threadIdx.x & 63) == 0) {
         atomicMax((unsigned long long*)&dom->hmax_new_bits, (unsigned long long)ord_bits(hm));
-        bool bad = false;
-        for (int k = 0; k < 3; ++k)
-            if (P.periodic[k] && !(4.0 * hm < P.L[k])) bad = true;
-        if (bad && hm > 0.0) set_err(dom, SPH_ERRBIT_CELL_RANGE);
+        if (hm > 0.0) check_cell_range(P, dom, hm);
     }
 }
 
 // symmetric neighbour lists: gather members of N(a) from the front of the
-// column, members of N_s(a) \ N(a) from the back
+// tile row, members of N_s(a) \ N(a) from the back
 __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __restrict__ dom,
-                                                           const int32_t* __restrict__ cs,
-                                                           const int32_t* __restrict__ ce,
-                                                           const double* __restrict__ chmax,
-                                                           const double* __restrict__ x,
-                                                           const double* __restrict__ y,
-                                                           const double* __restrict__ z,
-                                                           const double* __restrict__ h,
+                                                           const CellRange* __restrict__ cells,
+                                                           const Pos4* __restrict__ p4,
                                                            int32_t* __restrict__ nc,
                                                            int32_t* __restrict__ ns,
                                                            int32_t* __restrict__ list)
@@ -203,30 +252,30 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
     const int64_t a = lb * kBlock + threadIdx.x;
     if (a >= P.n) return;
     const Domain D = *dom;
-    const double xa = x[a], ya = y[a], za = z[a], ha = h[a];
+    const Pos4 pa = p4[a];
+    const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
     const double hnew = ord_value(D.hmax_new_bits);
     const double ha2 = 2.0 * ha;
     const double Ra2 = ha2 * ha2;
     const int ng = P.ng_max;
-    const int64_t st = P.stride;
     int cg = 0, co = 0;
     walk_cells(
-        P, D, cs, ce, xa, ya, za, 2.0 * fmax(ha, hnew),
-        [&](uint64_t cid, double g2) {
-            double hc = 2.0 * fmax(ha, chmax[cid]);
+        P, D, cells, p4, xa, ya, za, 2.0 * fmax(ha, hnew),
+        [&](const CellRange& cr, double g2) {
+            double hc = 2.0 * fmax(ha, cr.hmax);
             return g2 < hc * hc;
         },
-        [&](int32_t b) {
+        [&](int32_t b, const Pos4& q) {
             if (b == a) return;
             double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, x[b], y[b], z[b], dx, dy, dz);
+            double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
             if (r2 < Ra2) {
-                if (cg < ng) list[(int64_t)cg * st + a] = b;
+                if (cg < ng) list[lpos(a, cg, ng)] = b;
                 ++cg;
             } else {
-                double hb2 = 2.0 * fmax(ha, h[b]);
+                double hb2 = 2.0 * fmax(ha, q.h);
                 if (r2 < hb2 * hb2) {
-                    if (co < ng) list[(int64_t)(ng - 1 - co) * st + a] = b;
+                    if (co < ng) list[lpos(a, ng - 1 - co, ng)] = b;
                     ++co;
                 }
             }
@@ -236,27 +285,205 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
     if (cg + co > ng) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
 }
 
+// ---------------------------------------------------------------- fused step
+// candidates: b != a with r^2 < (2 kappa max(h0_a, h0_b))^2
+__global__ __launch_bounds__(kBlock) void k_candidates(Params P, Domain* __restrict__ dom,
+                                                       const CellRange* __restrict__ cells,
+                                                       const Pos4* __restrict__ p4,
+                                                       int32_t* __restrict__ nk,
+                                                       int32_t* __restrict__ cand)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    if (a >= P.n) return;
+    const Domain D = *dom;
+    const Pos4 pa = p4[a];
+    const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
+    const double kap = P.kappa;
+    const double hmax0 = ord_value(D.hmax_new_bits);
+    const int cap = P.cand_cap;
+    int k = 0;
+    walk_cells(
+        P, D, cells, p4, xa, ya, za, 2.0 * kap * fmax(ha, hmax0),
+        [&](const CellRange& cr, double g2) {
+            double hc = 2.0 * kap * fmax(ha, cr.hmax);
+            return g2 < hc * hc;
+        },
+        [&](int32_t b, const Pos4& q) {
+            if (b == a) return;
+            double dx, dy, dz;
+            double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
+            double R = 2.0 * kap * fmax(ha, q.h);
+            if (r2 < R * R) {
+                if (k < cap) cand[lpos(a, k, cap)] = b;
+                ++k;
+            }
+        });
+    nk[a] = k;
+    if (k > cap) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
+}
+
+// Newton iterations summing over the candidate list (self term added: S(0) = 1)
+__global__ __launch_bounds__(kBlock) void k_update_h_list(Params P, Domain* __restrict__ dom,
+                                                          const int32_t* __restrict__ nk,
+                                                          const int32_t* __restrict__ cand,
+                                                          const Pos4* __restrict__ p4,
+                                                          double* __restrict__ h)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    if (a >= P.n) return;
+    const Pos4 pa = p4[a];
+    const double xa = pa.x, ya = pa.y, za = pa.z;
+    const double h0 = pa.h;
+    const int cap = P.cand_cap;
+    const int cnt = min(nk[a], cap);
+    double hc = h0;
+    for (int it = 0; it < P.newton_iters; ++it) {
+        const double h2 = 2.0 * hc;
+        const double R2 = h2 * h2;
+        const double tsc = kPiHalfSq / (hc * hc);
+        double sS = 1.0, sV = 0.0;
+        for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+            int32_t bb[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u)
+                bb[u] = (j0 + u < cnt) ? cand[lpos(a, j0 + u, cap)] : (int32_t)a;
+            double qx[kBatch], qy[kBatch], qz[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const Pos4* q = p4 + bb[u];
+                qx[u] = q->x; qy[u] = q->y; qz[u] = q->z;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                double dx, dy, dz;
+                double r2 = disp(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
+                if (j0 + u < cnt && r2 < R2) {
+                    double S, vdS;
+                    sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
+                    sS += S;
+                    sV += vdS;
+                }
+            }
+        }
+        hc = newton_step(P, hc, h0, sS, sV);
+    }
+    h[a] = hc;
+    check_cell_range(P, dom, hc);
+}
+
+// exact lists from the candidates with the final h (same layout as k_find_neighbors)
+__global__ __launch_bounds__(kBlock) void k_filter(Params P, Domain* __restrict__ dom,
+                                                   const int32_t* __restrict__ nk,
+                                                   const int32_t* __restrict__ cand,
+                                                   const Pos4* __restrict__ p4,
+                                                   int32_t* __restrict__ nc,
+                                                   int32_t* __restrict__ ns,
+                                                   int32_t* __restrict__ list)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    if (a >= P.n) return;
+    const Pos4 pa = p4[a];
+    const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
+    const double ha2 = 2.0 * ha;
+    const double Ra2 = ha2 * ha2;
+    const int cap = P.cand_cap;
+    const int cnt = min(nk[a], cap);
+    const int ng = P.ng_max;
+    int cg = 0, co = 0;
+    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+        int32_t bb[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            bb[u] = (j0 + u < cnt) ? cand[lpos(a, j0 + u, cap)] : (int32_t)a;
+        Pos4 q[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) q[u] = p4[bb[u]];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (j0 + u >= cnt) continue;
+            const int32_t b = bb[u];
+            double dx, dy, dz;
+            double r2 = disp(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
+            if (r2 < Ra2) {
+                if (cg < ng) list[lpos(a, cg, ng)] = b;
+                ++cg;
+            } else {
+                double hb2 = 2.0 * fmax(ha, q[u].h);
+                if (r2 < hb2 * hb2) {
+                    if (co < ng) list[lpos(a, ng - 1 - co, ng)] = b;
+                    ++co;
+                }
+            }
+        }
+    }
+    nc[a] = cg;
+    ns[a] = cg + co;
+    if (cg + co > ng) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
+}
+
 }  // namespace
 
+int candidate_capacity(int ng_max)
+{
+    // the candidate reach is at most kFusedKappaMax times the list reach:
+    // kFusedKappaMax^3 times the volume, with 25% headroom
+    double c = ng_max * kFusedKappaMax * kFusedKappaMax * kFusedKappaMax * 1.25;
+    int cap = (int)ceil(c);
+    return cap > 8192 ? 8192 : cap;
+}
+
 hipError_t launch_update_h(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                           hipStream_t s)
+                           hipStream_t s, bool pack)
 {
     if (P.newton_iters == 0) return hipSuccess;
+    if (pack) {
+        hipError_t e = launch_pack_p4(P, W, p, s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    k_update_h<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cstart, W.cend, p->x, p->y, p->z,
-                                               p->h);
+    k_update_h<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, p->h);
     return hipGetLastError();
 }
 
+// always repacks: h may have changed since the cell build
 hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
                                  const sph_particles* p, hipStream_t s)
+{
+    hipError_t e = launch_pack_p4(P, W, p, s);
+    if (e != hipSuccess) return e;
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
+    int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
+    k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, L.ncells_cap);
+    k_find_neighbors<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nc, W.ns,
+                                                     W.list);
+    return hipGetLastError();
+}
+
+// fused: candidates at h0, Newton over candidates, exact lists at the new h.
+// Expects the packed positions of the cell build (h0 in them).
+hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
+                                hipStream_t s)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
-    k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cstart, W.cend, p->h, W.chmax, L.ncells_cap);
-    k_find_neighbors<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cstart, W.cend, W.chmax, p->x,
-                                                     p->y, p->z, p->h, W.nc, W.ns, W.list);
+    k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, L.ncells_cap);
+    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand);
+    if (P.newton_iters > 0)
+        k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h);
+    hipError_t e = launch_pack_p4(P, W, p, s);
+    if (e != hipSuccess) return e;
+    k_filter<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns, W.list);
     return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsph.so")
+# SPH_LIBRARY selects another build of the library (e.g. one with other tuning flags)
+LIB_PATH = os.environ.get("SPH_LIBRARY") or os.path.join(_HERE, "libsph.so")
 
 SPH_OK = 0
 STATUS_NAMES = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_WORKSPACE",
@@ -283,15 +284,16 @@ def step(cfg: Config, parts: Particles, g: Globals, ws: Workspace, stream=None):
 
 
 def neighbors_view(cfg: Config, ws: Workspace):
-    """Returns (nc, ns, list) tensor views into ws; list has shape (ng_max, n)."""
+    """Returns (nc, ns, list) tensor views into ws; list has shape
+    (ceil(n/64), ng_max, 64): entry j of slot a is list[a // 64, j, a % 64]."""
     nc, ns, lst = C.c_void_p(), C.c_void_p(), C.c_void_p()
-    stride = C.c_int64()
+    cap = C.c_int32()
     _check(lib().sph_neighbors_view(C.byref(cfg.c()), ws.ptr, C.byref(nc), C.byref(ns),
-                                    C.byref(lst), C.byref(stride)), "sph_neighbors_view")
+                                    C.byref(lst), C.byref(cap)), "sph_neighbors_view")
     n = cfg.n
+    tiles = (n + 63) // 64
     return (ws.view(nc.value, n, torch.int32), ws.view(ns.value, n, torch.int32),
-            ws.view(lst.value, cfg.ng_max * stride.value, torch.int32).view(cfg.ng_max,
-                                                                              stride.value))
+            ws.view(lst.value, tiles * cap.value * 64, torch.int32).view(tiles, cap.value, 64))
 
 
 def order_view(cfg: Config, ws: Workspace):

@@ -48,15 +48,17 @@ class Run:
         nc, ns, lst = sph.neighbors_view(self.cfg, self.ws)
         nc = nc.cpu().numpy().astype(np.int64)
         ns = ns.cpu().numpy().astype(np.int64)
-        lst = lst.cpu().numpy()
+        lst = lst.cpu().numpy()                     # (tiles, ng_max, 64)
         ids = self.ids()
         ng = self.cfg.ng_max
+        n = ids.size
         rows = []
         for j in range(ng):
+            col = lst[:, j, :].reshape(-1)[:n]      # entry j of every slot
             a_g = np.nonzero(j < nc)[0]
-            rows.append(np.stack([ids[a_g], ids[lst[j, a_g]], np.ones_like(a_g)], 1))
+            rows.append(np.stack([ids[a_g], ids[col[a_g]], np.ones_like(a_g)], 1))
             a_s = np.nonzero(j >= ng - (ns - nc))[0]
-            rows.append(np.stack([ids[a_s], ids[lst[j, a_s]], np.zeros_like(a_s)], 1))
+            rows.append(np.stack([ids[a_s], ids[col[a_s]], np.zeros_like(a_s)], 1))
         P = np.concatenate(rows)
         P = P[np.lexsort((P[:, 1], P[:, 0]))]
         cnt_nc = np.empty_like(nc)

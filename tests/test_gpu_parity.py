@@ -188,7 +188,16 @@ def test_full_steps(name, steps):
     for s in range(steps):
         sph.step(cfg, r.parts, r.g, r.ws)
         assert r.status() == (0, 0)
+        before = st
         st, gl, f = oracle.step(ocfg, st, gl)
+        if s == 0:
+            # the step's lists (one shared cell walk) are the exact sets at the
+            # step-start positions and the updated h
+            P, nc, ns = r.neighbor_pairs()
+            nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, before["x"], before["y"],
+                                                       before["z"], f["h"])
+            assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
+            assert np.array_equal(P, oracle_pairs(lists, gath))
         G = r.g.host()
         assert abs(G["dt"] - gl["dt"]) <= TOL * gl["dt"], s
         assert abs(G["t"] - gl["t"]) <= TOL * gl["t"], s
