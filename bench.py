@@ -1,13 +1,19 @@
 """Benchmark of the SPH time step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
-                    [--precision fp64|mixed] [--no-cpu-baseline]
+                    [--precision fp64|mixed] [--no-cpu-baseline] [--no-mixed]
+                    [--no-adjoint]
 
 A step is one sph_step (Morton sort into cells, Newton h update, neighbour
 search, density, IAD, momentum/energy with AV, global dt, integration and
 conservation sums) on the synthetic workload with every input resident in HBM.
 The set-up (initial conditions, upload, the Newton initialisation of h and the
-reference density) is untimed.  Prints ONE JSON line.
+reference density) is untimed.  The timed steps run through sph_step_marked
+(the same launches plus HIP events between phases) so the per-phase times and
+the roofline of the longest phase come from the timed steps themselves.  Then,
+unless switched off: the same workload in mixed precision, the adjoint/forward
+time of the 64^3 rollout, and the FP64 oracle timed on the host on a bounded
+sample.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -35,27 +41,34 @@ WORKLOADS = {
            "c4_square_patch"),
 }
 
-# Algorithmic FP64 flops of each stage per unit (per neighbour pair unless noted),
-# counted from the arithmetic the method needs (see the design notes): sinc^n and
-# v dS/dv by even polynomials, one sqrt only in the viscosity branch.
+# Algorithmic work of each phase of sph_step (the per-unit figures are derived in
+# the design notes).  Flops are FP64 operations (an fma counts 2) of the
+# arithmetic the phase needs per unit: neighbour pair for the pair passes
+# (k_g gather pairs, k_s symmetric pairs per particle), candidate pair for the
+# Newton iterations.  Bytes are HBM bytes with every datum read or written once.
 FLOPS_PER_PAIR = {
-    "update_h": 2 * 30,     # two Newton iterations, ~30 flops per pair each
-    "find_neighbors": 10,   # distance test per neighbour
-    "density": 45,
-    "iad": 35,
-    "momentum_energy": 110,
+    "newton_h": 80,          # per candidate pair and iteration: r^2, S and v dS/dv series
+    "density": 80,           # r^2, S and v dS/dv by 16- and 15-term series, two sums
+    "iad": 63,               # r^2, S series, V W, six d_i d_j products accumulated
+    "momentum_energy": 175,  # r^2, W(h_a) and W(h_b), C_a d and C_b d, AV, a and du terms
 }
-# algorithmic HBM bytes per particle of each stage (lists counted where read/written)
-def bytes_per_particle(stage, k_g, k_s, wc):
+
+
+def bytes_per_particle(phase, k_g, k_s, wc):
+    """Algorithmic HBM bytes per particle of one phase of sph_step."""
     return {
-        "build_cells": 32 + 36 + 24 + (260 if wc else 228) + 8,
-        "update_h": 72,
-        "find_neighbors": 36 + 4 * k_s + 8,
-        "density": (96 if wc else 80) + 4 * k_g,
-        "iad": 96 + 4 * k_g,
-        "momentum_energy": 176 + 4 * k_s,
-        "timestep_integrate": 184,
-    }[stage]
+        # bbox (x y z h), keys, 8 radix passes over 8-byte keys and 4-byte indices,
+        # permutation of the state (15 fields with the weakly compressible EOS,
+        # else 13, plus the id), cell table fill
+        "build_cells": 32 + 12 + 8 * 24 + (16 if wc else 14) * 16 + 32 + 8,
+        "candidates": 32 + 4,                         # p4 read, count write (+ lists below)
+        "newton_h": 32 + 8,                           # p4 read, h write (+ lists below)
+        "lists": 64 + 8 + 4 * k_s,                    # p4 repack, counts, filtered list
+        "density": (100 if wc else 84) + 4 * k_g,     # p4 m u (p_ref rho_ref), out 4 fields
+        "iad": 24 + 32 + 72 + 4 + 4 * k_g + 48 + 128,  # vol, p4, rec sources, list, C, records
+        "momentum_energy": 32 + 128 + 8 + 8 + 4 * k_s + 32,  # p4, record, u, counts, list, out
+        "integrate": 13 * 8 + 4 * 8 + 11 * 8,          # state + rates in, state out
+    }[phase]
 
 
 def parse():
@@ -66,8 +79,11 @@ def parse():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-stage-timing", action="store_true")
-    ap.add_argument("--cpu-sample-side", type=int, default=32,
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision timing of the same workload")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward timing of the 64^3 rollout")
+    ap.add_argument("--cpu-sample-side", type=int, default=48,
                     help="side of the square-patch lattice the oracle steps on")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (scales HBM counters)")
@@ -78,27 +94,65 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stage_times(sph, cfg, parts, g, ws, steps, torch):
-    """Average per-stage time (ms) over `steps` steps run stage by stage, with HIP
-    events recorded on the stream the library launches on (torch's current one)."""
-    names = ["build_cells", "update_h", "find_neighbors", "density", "iad",
-             "momentum_energy", "timestep_integrate"]
-    acc = {k: 0.0 for k in names}
-    for _ in range(steps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-        ev[0].record()
-        sph.build_cells(cfg, parts, ws); ev[1].record()
-        sph.update_h(cfg, parts, ws); ev[2].record()
-        sph.find_neighbors(cfg, parts, ws); ev[3].record()
-        sph.density(cfg, parts, ws); ev[4].record()
-        sph.iad(cfg, parts, ws); ev[5].record()
-        sph.momentum_energy(cfg, parts, ws); ev[6].record()
-        sph.timestep(cfg, g, ws)
-        sph.integrate(cfg, parts, g, ws); ev[7].record()
+def roofline(phases, n, k_g, k_s, wc, iters):
+    """Roofline of the phase that takes the longest.  Both ceilings are evaluated
+    (algorithmic HBM bytes against 8 TB/s, algorithmic FP64 flops against the
+    78.6 TFLOP/s vector peak); the binding one (larger fraction) is reported."""
+    dom = max(phases, key=phases.get)
+    t = phases[dom] * 1e-3
+    by = bytes_per_particle(dom, k_g, k_s, wc)
+    hbm = by * n / t / 1e9
+    res = {"kernel": dom, "phase_ms": phases[dom], "traffic": None}
+    pairs = {"newton_h": None, "density": k_g * n, "iad": k_g * n, "momentum_energy": k_s * n}
+    if dom in FLOPS_PER_PAIR and pairs[dom] is not None:
+        fl = FLOPS_PER_PAIR[dom] * pairs[dom]
+        alu = fl / t / 1e12
+        res["alt"] = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": hbm / HBM_PEAK_GBS}
+        if alu / FP64_VALU_PEAK_TFLOPS >= hbm / HBM_PEAK_GBS:
+            res.update(bound="alu", achieved=alu, peak=FP64_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                       frac=alu / FP64_VALU_PEAK_TFLOPS,
+                       algorithmic=f"{FLOPS_PER_PAIR[dom]} FP64 flops per pair x "
+                                   f"{pairs[dom]:.4e} pairs")
+            return res
+    res.update(bound="hbm", achieved=hbm, peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=hbm / HBM_PEAK_GBS,
+               algorithmic=f"{by:.1f} B per particle x {n} particles")
+    return res
+
+
+def adjoint_timing(sph, inputs, torch, steps=20, ckpt=5):
+    """Forward and reverse time of the 64^3 lattice rollout (20 steps, a
+    checkpoint every 5, density loss against a seeded target field)."""
+    w = inputs.c5_lattice()
+    cfg = sph.Config.from_params(w.n, w.params)
+    parts = sph.Particles.from_arrays(w.arrays, cfg)
+    ws = sph.Workspace(cfg)
+    g = sph.Globals()
+    sph.initialise(cfg, parts, ws, g)
+    target = torch.tensor(inputs.c5_target_density(w.n), device="cuda")
+    v0 = torch.tensor(np.stack([w.arrays["vx"], w.arrays["vy"], w.arrays["vz"]], 1),
+                      device="cuda", requires_grad=True)
+    ro = sph.Rollout(cfg, parts, g, ws, steps=steps, ckpt=ckpt)
+    for _ in range(2):   # first pass warms up
+        v0.grad = None
         torch.cuda.synchronize()
-        for i, k in enumerate(names):
-            acc[k] += ev[i].elapsed_time(ev[i + 1])
-    return {k: v / steps for k, v in acc.items()}
+        t0 = time.perf_counter()
+        rho = sph.DensityRollout.apply(v0, ro)
+        loss = 0.5 * ((rho - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    st, bits = sph.status_sync(ws)
+    if st:
+        raise RuntimeError(f"adjoint rollout raised {sph.status_string(st)} (bits {bits})")
+    fwd, bwd = (t1 - t0) * 1e3, (t2 - t1) * 1e3
+    return {"workload": f"lattice 64^3 = {w.n} particles, {steps}-step rollout, checkpoint "
+                        f"every {ckpt}, loss 1/2|rho - rho*|^2, gradient w.r.t. v0",
+            "forward_ms": fwd, "backward_ms": bwd, "adjoint_over_forward": bwd / fwd,
+            "loss": float(loss.item()), "grad_norm": float(v0.grad.norm().item())}
 
 
 def cpu_baseline(side):
@@ -158,24 +212,28 @@ def main():
     log("[bench] warm-up done")
 
     stream = torch.cuda.current_stream()
+    marks = [sph.StepMarks(stream) for _ in range(args.steps)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     for i in range(args.steps):
-        sph.step(cfg, parts, g, ws)
+        sph.step_marked(cfg, parts, g, ws, marks[i])
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     st, bits = sph.status_sync(ws)
     if st:
         raise RuntimeError(f"timed steps raised {sph.status_string(st)} (bits {bits})")
-    log(f"[bench] {args.steps} timed steps: {ms:.3f} ms/step")
+    phases = {k: 0.0 for k in sph.STEP_PHASES}
+    for mk in marks:
+        for k, v in mk.phase_ms().items():
+            phases[k] += v / args.steps
+    log(f"[bench] {args.steps} timed steps: {ms:.3f} ms/step; phases "
+        + " ".join(f"{k}={v:.2f}" for k, v in phases.items()))
 
     nc, ns, _ = sph.neighbors_view(cfg, ws)
     k_g = float(nc.double().mean())
     k_s = float(ns.double().mean())
-    pairs_g = float(nc.double().sum())
-    pairs_s = float(ns.double().sum())
     n = cfg.n
     wc = cfg.eos == 1
 
@@ -191,33 +249,35 @@ def main():
         "config": {"workload": desc, "particles": n, "neighbours_gather_mean": k_g,
                    "neighbours_symmetric_mean": k_s, "ng_max": cfg.ng_max,
                    "newton_iters": cfg.newton_iters},
+        "phase_ms": {k: round(v, 4) for k, v in phases.items()},
     }
+    out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters)
+    step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc) for k in phases) * n
+    out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
-    if not args.no_stage_timing:
-        stt = stage_times(sph, cfg, parts, g, ws, args.steps, torch)
-        out["stage_ms"] = {k: round(v, 4) for k, v in stt.items()}
-        dom = max(stt, key=stt.get)
-        t = stt[dom] * 1e-3
-        unit_pairs = {"update_h": pairs_g, "find_neighbors": pairs_s, "density": pairs_g,
-                      "iad": pairs_g, "momentum_energy": pairs_s}
-        if dom in FLOPS_PER_PAIR:
-            fl = FLOPS_PER_PAIR[dom] * unit_pairs[dom]
-            ach = fl / t / 1e12
-            out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": ach,
-                               "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                               "frac": ach / FP64_VALU_PEAK_TFLOPS, "traffic": None,
-                               "algorithmic": f"{FLOPS_PER_PAIR[dom]} FP64 flops per neighbour "
-                                              f"pair x {unit_pairs[dom]:.3e} pairs"}
-        else:
-            by = bytes_per_particle(dom, k_g, k_s, wc) * n
-            ach = by / t / 1e9
-            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach,
-                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                               "traffic": None,
-                               "algorithmic": f"{bytes_per_particle(dom, k_g, k_s, wc)} B per "
-                                              f"particle x {n} particles"}
-        step_bytes = sum(bytes_per_particle(s, k_g, k_s, wc) for s in stt) * n
-        out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    if not args.no_mixed and prec == sph.FP64:
+        mcfg = cfg.replace(precision=sph.MIXED)
+        sph.step(mcfg, parts, g, ws)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(args.steps):
+            sph.step(mcfg, parts, g, ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        mms = e0.elapsed_time(e1) / args.steps
+        st, bits = sph.status_sync(ws)
+        if st:
+            raise RuntimeError(f"mixed steps raised {sph.status_string(st)} (bits {bits})")
+        out["mixed"] = {"ms_per_step": mms, "value": n / (mms * 1e-3),
+                        "speedup_vs_fp64": ms / mms,
+                        "note": "same workload and state, FP32 pair terms with FP64 sums"}
+        log(f"[bench] mixed precision: {mms:.3f} ms/step")
+    del parts, ws
+    torch.cuda.empty_cache()
+
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_timing(sph, inputs, torch)
+        log(f"[bench] adjoint rollout: {out['adjoint']}")
 
     if args.calib_copy_mib > 0:
         # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE counters calibrate

@@ -193,6 +193,70 @@ sph_status sph_integrate(const sph_config* cfg, sph_particles* p, sph_globals* g
 sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
                     sph_stream stream);
 
+/* sph_step with phase markers, for timing the step's kernels on its own stream.
+ * Enqueues exactly the launches of sph_step and records events[k] (hipEvent_t
+ * handles created by the caller, (host) array of SPH_STEP_PHASES + 1) after
+ * phase k: 0 start; 1 cell build; 2 candidate walk (fused path; walk path:
+ * the h update); 3 Newton h update (walk path: empty); 4 neighbour lists;
+ * 5 density; 6 IAD; 7 momentum/energy and the time step; 8 integration and
+ * sums.  Returns SPH_E_ARG if nevents differs or a handle is NULL. */
+#define SPH_STEP_PHASES 8
+sph_status sph_step_marked(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                           sph_stream stream, void* const* events, int32_t nevents);
+
+/* ------------------------------------------------------------------------
+ * Reverse mode (adjoint) of one step.  The map differentiated is the step of
+ * section 4.1 with its STRUCTURE FROZEN: the smoothing lengths h, the time
+ * steps dt and dt_m1, the neighbour sets and the artificial-viscosity branches
+ * (v_ab . x_ab < 0) are those of the forward step and are not differentiated
+ * (the set indicators and the clamp have zero derivative almost everywhere).
+ * The masses are constants.  FP64 only (precision must be SPH_FP64).
+ * ---------------------------------------------------------------------- */
+
+/* Gradient arrays (device, caller-owned, FP64, length n) of the fields one
+ * step maps: x^n, v^n, v^{n-1/2}, u, du_m1 (the others are constants of the
+ * frozen step). */
+typedef struct {
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *vhx, *vhy, *vhz;
+    double *u, *du_m1;
+} sph_grads;
+
+/* (host) Bytes of the adjoint workspace for cfg (224 B per particle plus
+ * alignment; a pure function of n).  Returns 0 if cfg is invalid. */
+size_t sph_adjoint_workspace_bytes(const sph_config* cfg);
+
+/* Vector-Jacobian product of one sph_step.
+ * In:  p, g and ws exactly as they were when the forward sph_step was called
+ *      (the step's input state, e.g. restored from a checkpoint, with g->dt_m1
+ *      of that step); gout: adjoints of the step's outputs x, v, vh, u, du_m1,
+ *      per slot of the order the forward step left the particles in.
+ * Out: gin: adjoints of the step's inputs, per slot of the order p has on
+ *      entry (the permutation of the cell build is undone: it is linear and its
+ *      adjoint is its inverse).  gin may alias gout.
+ * The call first re-runs the forward stages of the step (cell build, h update,
+ * lists, density, IAD, momentum/energy, time step; not the integration), so
+ * on return p is in the step's slot order with every stage output filled and
+ * g->dt set, as after those stages of sph_step; the other fields of g are
+ * unchanged.  Then, in gather form over the symmetric lists (no atomics,
+ * bitwise reproducible): integrate^T, momentum/energy^T with the EOS^T and
+ * tau_bar = -C Cbar C, IAD^T, density^T (eq. 1 with the grad-h term).
+ * adj_ws: sph_adjoint_workspace_bytes, 256-byte aligned, no initialisation. */
+sph_status sph_step_backward(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                             void* adj_ws, const sph_grads* gout, sph_grads* gin,
+                             sph_stream stream);
+
+/* Vector-Jacobian product of the density (eq. 1) with respect to positions,
+ * h frozen: x_bar = (d rho / d x)^T rho_bar, for a loss on the density.
+ * In:  the state of a completed sph_build_cells -> (update_h) -> find_neighbors
+ *      -> sph_density sequence on ws and p; rho_bar per slot of the current order.
+ * Out: x_bar, y_bar, z_bar per slot of the order before that sph_build_cells
+ *      (the cell build's permutation is undone).  They must not alias rho_bar. */
+sph_status sph_density_backward(const sph_config* cfg, const sph_particles* p, void* ws,
+                                void* adj_ws, const double* rho_bar, double* x_bar,
+                                double* y_bar, double* z_bar, sph_stream stream);
+
 /* (host) Device pointers into ws after sph_find_neighbors or sph_step: nc, ns
  * (int32[n]) and the list (int32, tiled by 64 slots so that a wavefront's
  * entries are contiguous: entry j of slot a is at

@@ -169,3 +169,37 @@ def step(S: Setup, st: dict, dt: float, dt_m1: float, p_ref=None, rho_ref=None):
         u1 = u + dt * du
     new = {"x": x1, "v": v1, "vh": vh1, "u": u1, "du_m1": du}
     return new, {"rho": rho, "omega": omega, "p": p, "c": c, "C": Cm, "a": acc, "du": du}
+
+
+def rollout_density(cfg, st0: dict, v0, steps: int):
+    """Final density after `steps` steps from the state st0 with v = vh = v0.
+
+    v0 is a torch (n, 3) float64 tensor (it may require grad); st0 holds numpy
+    arrays keyed like the C oracle's state.  The structure of each step is the C
+    oracle's and is frozen: its Newton h and its dt (sections 4.1 and 4.2), and the
+    final evaluation's h (one more h update on the final positions).  Then the
+    steps are replayed with this module's differentiable step map.  Returns
+    (rho, frozen) with frozen the per-step (h, dt, dt_m1) list and the final h."""
+    import numpy as np
+    import oracle as ora
+
+    v = v0.detach().cpu().numpy()
+    st = dict(st0)
+    for c, a in enumerate("xyz"):
+        st["v" + a] = v[:, c].copy()
+        st["vh" + a] = v[:, c].copy()
+    gl = {"dt_m1": 0.0, "t": 0.0}
+    frozen = []
+    for _ in range(steps):
+        new, g, f = ora.step(cfg, st, gl)
+        frozen.append((f["h"], g["dt"], gl["dt_m1"]))
+        st, gl = new, g
+    h_final = ora.update_h(cfg, st["x"], st["y"], st["z"], st["h"])
+    ts = {"x": torch.tensor(np.stack([st0["x"], st0["y"], st0["z"]], 1)),
+          "v": v0, "vh": v0,
+          "u": torch.tensor(st0["u"]),
+          "du_m1": torch.tensor(st0.get("du_m1", np.zeros(st0["u"].size)))}
+    for h, dt, dt_m1 in frozen:
+        ts, _ = step(Setup(cfg, st0["m"], h), ts, dt, dt_m1)
+    rho, _ = density_omega(Setup(cfg, st0["m"], h_final), ts["x"])
+    return rho, frozen, h_final

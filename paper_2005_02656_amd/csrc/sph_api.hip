@@ -317,39 +317,130 @@ sph_status sph_integrate(const sph_config* cfg, sph_particles* p, sph_globals* g
     return hip_status(launch_integrate(c.P, c.W, p, g, c.s));
 }
 
+}  // extern "C"
+
+namespace {
+
+bool step_args_ok(const sph_config* cfg, const sph_particles* p, const sph_globals* g)
+{
+    return g && state_ok(cfg, p) && p->rho && p->omega && p->p && p->c && p->c11 && p->c12 &&
+           p->c13 && p->c22 && p->c23 && p->c33 && p->ax && p->ay && p->az && p->du;
+}
+
+// every stage of the step up to and including the time step (not the integration);
+// mk marks the phases: 1 cell build, 2 candidates, 3 Newton h, 4 lists, 5 density,
+// 6 IAD, 7 momentum/energy and time step (the walk-based path marks 2-4 after
+// update_h, update_h and find_neighbors)
+sph_status step_rates(Ctx& c, sph_particles* p, sph_globals* g, const Marks& mk = Marks())
+{
+    hipError_t e;
+    if ((e = launch_build_cells(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    mk.at(1, c.s);
+    // the cell build packs positions; with a small clamp ratio one cell walk
+    // feeds both the Newton iterations and the lists (fused), else the walks of
+    // the stage entry points run; the IAD pass writes the momentum records
+    if (c.P.cand_cap > 0) {
+        Marks sub;
+        if (mk.ev && mk.n > 2) sub = Marks{mk.ev + 2, mk.n - 2};
+        if ((e = launch_fused_h_lists(c.P, c.L, c.W, p, c.s, sub))) return SPH_E_HIP;
+    } else {
+        if ((e = launch_update_h(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+        mk.at(2, c.s);
+        mk.at(3, c.s);
+        if ((e = launch_find_neighbors(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
+    }
+    mk.at(4, c.s);
+    if (c.P.precision == SPH_MIXED) {
+        if ((e = launch_density_mixed(c.P, c.L, c.W, p, c.s, true))) return SPH_E_HIP;
+        mk.at(5, c.s);
+        if ((e = launch_iad_mixed(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
+        mk.at(6, c.s);
+        if ((e = launch_momentum_energy_mixed(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+    } else {
+        if ((e = launch_density(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+        mk.at(5, c.s);
+        if ((e = launch_iad(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
+        mk.at(6, c.s);
+        if ((e = launch_momentum_energy(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+    }
+    if ((e = launch_timestep(c.P, c.W, g, c.s))) return SPH_E_HIP;
+    mk.at(7, c.s);
+    return SPH_OK;
+}
+
+bool grads_ok(const sph_grads* q)
+{
+    if (!q) return false;
+    const void* f[] = {q->x, q->y, q->z, q->vx, q->vy, q->vz, q->vhx, q->vhy, q->vhz, q->u,
+                       q->du_m1};
+    for (const void* v : f)
+        if (!v) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
                     sph_stream stream)
 {
     Ctx c;
     sph_status st = prepare(cfg, ws, stream, c);
     if (st) return st;
-    if (!g || !state_ok(cfg, p) || !p->rho || !p->omega || !p->p || !p->c || !p->c11 ||
-        !p->c12 || !p->c13 || !p->c22 || !p->c23 || !p->c33 || !p->ax || !p->ay || !p->az ||
-        !p->du)
-        return SPH_E_ARG;
-    hipError_t e;
-    if ((e = launch_build_cells(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    // the cell build packs positions; with a small clamp ratio one cell walk
-    // feeds both the Newton iterations and the lists (fused), else the walks of
-    // the stage entry points run; the IAD pass writes the momentum records
-    if (c.P.cand_cap > 0) {
-        if ((e = launch_fused_h_lists(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    } else {
-        if ((e = launch_update_h(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
-        if ((e = launch_find_neighbors(c.P, c.L, c.W, p, c.s))) return SPH_E_HIP;
-    }
-    if (c.P.precision == SPH_MIXED) {
-        if ((e = launch_density_mixed(c.P, c.L, c.W, p, c.s, true))) return SPH_E_HIP;
-        if ((e = launch_iad_mixed(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
-        if ((e = launch_momentum_energy_mixed(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
-    } else {
-        if ((e = launch_density(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
-        if ((e = launch_iad(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
-        if ((e = launch_momentum_energy(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
-    }
-    if ((e = launch_timestep(c.P, c.W, g, c.s))) return SPH_E_HIP;
-    if ((e = launch_integrate(c.P, c.W, p, g, c.s))) return SPH_E_HIP;
-    return SPH_OK;
+    if (!step_args_ok(cfg, p, g)) return SPH_E_ARG;
+    if ((st = step_rates(c, p, g))) return st;
+    return hip_status(launch_integrate(c.P, c.W, p, g, c.s));
+}
+
+sph_status sph_step_marked(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                           sph_stream stream, void* const* events, int32_t nevents)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!step_args_ok(cfg, p, g) || !events || nevents != SPH_STEP_PHASES + 1) return SPH_E_ARG;
+    for (int k = 0; k < nevents; ++k)
+        if (!events[k]) return SPH_E_ARG;
+    Marks mk{(hipEvent_t*)events, nevents};
+    mk.at(0, c.s);
+    if ((st = step_rates(c, p, g, mk))) return st;
+    hipError_t e = launch_integrate(c.P, c.W, p, g, c.s);
+    mk.at(8, c.s);
+    return hip_status(e);
+}
+
+size_t sph_adjoint_workspace_bytes(const sph_config* cfg)
+{
+    if (!config_ok(cfg)) return 0;
+    return adjoint_workspace_bytes(cfg->n);
+}
+
+sph_status sph_step_backward(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
+                             void* adj_ws, const sph_grads* gout, sph_grads* gin,
+                             sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (cfg->precision != SPH_FP64) return SPH_E_ARG;
+    if (!adj_ws || ((uintptr_t)adj_ws & 255)) return SPH_E_WORKSPACE;
+    if (!step_args_ok(cfg, p, g) || !grads_ok(gout) || !grads_ok(gin)) return SPH_E_ARG;
+    if ((st = step_rates(c, p, g))) return st;
+    return hip_status(launch_step_backward(c.P, c.W, p, g, gout, gin, adj_ws, c.s));
+}
+
+sph_status sph_density_backward(const sph_config* cfg, const sph_particles* p, void* ws,
+                                void* adj_ws, const double* rho_bar, double* x_bar,
+                                double* y_bar, double* z_bar, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!adj_ws || ((uintptr_t)adj_ws & 255)) return SPH_E_WORKSPACE;
+    if (!p || !p->m || !rho_bar || !x_bar || !y_bar || !z_bar) return SPH_E_ARG;
+    return hip_status(launch_density_backward(c.P, c.W, p, rho_bar, x_bar, y_bar, z_bar, adj_ws,
+                                              c.s));
 }
 
 sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,

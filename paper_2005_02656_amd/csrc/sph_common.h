@@ -303,11 +303,30 @@ hipError_t launch_iad_mixed(const Params& P, const Layout& L, const Ws& W, sph_p
                             hipStream_t s, bool pack, bool write_rec);
 hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const Ws& W,
                                         sph_particles* p, hipStream_t s, bool pack);
+// Optional phase markers: event k is recorded on the stream once phase k's
+// launches are enqueued (sph_step_marked); no-ops without events.
+struct Marks {
+    hipEvent_t* ev = nullptr;
+    int n = 0;
+    void at(int k, hipStream_t s) const
+    {
+        if (ev && k < n) (void)hipEventRecord(ev[k], s);
+    }
+};
 hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                                hipStream_t s);
+                                hipStream_t s, const Marks& mk = Marks());
 hipError_t launch_timestep(const Params& P, const Ws& W, sph_globals* g, hipStream_t s);
 hipError_t launch_integrate(const Params& P, const Ws& W, sph_particles* p, sph_globals* g,
                             hipStream_t s);
 hipError_t launch_clear_domain(const Ws& W, hipStream_t s);
+// reverse mode (frozen structure): the forward stages of the step must have run
+// on W and p (lists, packed positions and records, stage outputs, g->dt)
+size_t adjoint_workspace_bytes(int64_t n);
+hipError_t launch_step_backward(const Params& P, const Ws& W, const sph_particles* p,
+                                const sph_globals* g, const sph_grads* gout, sph_grads* gin,
+                                void* adj_ws, hipStream_t s);
+hipError_t launch_density_backward(const Params& P, const Ws& W, const sph_particles* p,
+                                   const double* rho_bar, double* xb, double* yb, double* zb,
+                                   void* adj_ws, hipStream_t s);
 
 }  // namespace sph

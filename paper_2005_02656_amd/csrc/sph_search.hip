@@ -472,15 +472,17 @@ hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
 // fused: candidates at h0, Newton over candidates, exact lists at the new h.
 // Expects the packed positions of the cell build (h0 in them).
 hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                                hipStream_t s)
+                                hipStream_t s, const Marks& mk)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
     k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, L.ncells_cap);
     k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand);
+    mk.at(0, s);
     if (P.newton_iters > 0)
         k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h);
+    mk.at(1, s);
     hipError_t e = launch_pack_p4(P, W, p, s);
     if (e != hipSuccess) return e;
     k_filter<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns, W.list);

@@ -48,6 +48,13 @@ class _Config(C.Structure):
                 ("precision", C.c_int32), ("reserved", C.c_int32)]
 
 
+GRAD_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "u", "du_m1")
+
+
+class _Grads(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in GRAD_FIELDS]
+
+
 class _Particles(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in
                 ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",
@@ -126,6 +133,14 @@ _SIGS = {
                                      C.c_void_p, C.c_void_p]),
     "sph_order_view": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sph_status_sync": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_step_marked": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_int32]),
+    "sph_adjoint_workspace_bytes": (C.c_size_t, [C.c_void_p]),
+    "sph_step_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_density_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
     "sph_status_string": (C.c_char_p, [C.c_int]),
 }
 EXPORTED = tuple(_SIGS)
@@ -283,6 +298,35 @@ def step(cfg: Config, parts: Particles, g: Globals, ws: Workspace, stream=None):
            "sph_step")
 
 
+STEP_PHASES = ("build_cells", "candidates", "newton_h", "lists", "density", "iad",
+               "momentum_energy", "integrate")
+
+
+class StepMarks:
+    """HIP events (torch.cuda.Event, timing enabled) for sph_step_marked: one
+    before the step and one after each of its STEP_PHASES phases."""
+
+    def __init__(self, stream=None):
+        stream = stream or torch.cuda.current_stream()
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(len(STEP_PHASES) + 1)]
+        for e in self.events:     # torch creates the underlying event on first record
+            e.record(stream)
+        self.handles = (C.c_void_p * len(self.events))(*[e.cuda_event for e in self.events])
+
+    def phase_ms(self) -> dict:
+        """Per-phase durations (ms) of the last marked step (synchronises)."""
+        self.events[-1].synchronize()
+        return {k: self.events[i].elapsed_time(self.events[i + 1])
+                for i, k in enumerate(STEP_PHASES)}
+
+
+def step_marked(cfg: Config, parts: Particles, g: Globals, ws: Workspace, marks: StepMarks,
+                stream=None):
+    ps = parts.c()
+    _check(lib().sph_step_marked(C.byref(cfg.c()), C.byref(ps), g.ptr, ws.ptr, _stream(stream),
+                                 marks.handles, len(marks.events)), "sph_step_marked")
+
+
 def neighbors_view(cfg: Config, ws: Workspace):
     """Returns (nc, ns, list) tensor views into ws; list has shape
     (ceil(n/64), ng_max, 64): entry j of slot a is list[a // 64, j, a % 64]."""
@@ -330,3 +374,188 @@ def initialise(cfg: Config, parts: Particles, ws: Workspace, g: Globals, iters: 
         density(cfg, parts, ws, stream)
         parts.t["rho_ref"].copy_(parts.t["rho"])
     g.t.zero_()
+
+
+# --------------------------------------------------------------------------- adjoint
+class AdjointWorkspace:
+    """Caller-owned scratch of the reverse passes (sph_adjoint_workspace_bytes)."""
+
+    def __init__(self, cfg: Config, device="cuda"):
+        nbytes = lib().sph_adjoint_workspace_bytes(C.byref(cfg.c()))
+        if nbytes == 0:
+            raise SphError(1, "sph_adjoint_workspace_bytes (invalid config)")
+        self.raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.raw.data_ptr()) % 256
+        self.buf = self.raw[off:off + nbytes]
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+
+class Grads:
+    """Adjoints of the 11 fields one step maps (FP64 device tensors, length n)."""
+
+    def __init__(self, n: int, device="cuda"):
+        self.t = {k: torch.zeros(n, dtype=torch.float64, device=device) for k in GRAD_FIELDS}
+
+    def __getitem__(self, k):
+        return self.t[k]
+
+    def zero_(self):
+        for v in self.t.values():
+            v.zero_()
+        return self
+
+    def c(self) -> _Grads:
+        s = _Grads()
+        for k in GRAD_FIELDS:
+            setattr(s, k, C.c_void_p(self.t[k].data_ptr()))
+        return s
+
+
+def step_backward(cfg: Config, parts: Particles, g: Globals, ws: Workspace,
+                  aws: AdjointWorkspace, gout: Grads, gin: Grads, stream=None):
+    """Enqueues sph_step_backward: parts/g/ws must hold the step's INPUT state."""
+    ps, go, gi = parts.c(), gout.c(), gin.c()
+    _check(lib().sph_step_backward(C.byref(cfg.c()), C.byref(ps), g.ptr, ws.ptr, aws.ptr,
+                                   C.byref(go), C.byref(gi), _stream(stream)),
+           "sph_step_backward")
+
+
+def density_backward(cfg: Config, parts: Particles, ws: Workspace, aws: AdjointWorkspace,
+                     rho_bar: torch.Tensor, xb: torch.Tensor, yb: torch.Tensor, zb: torch.Tensor,
+                     stream=None):
+    """Enqueues sph_density_backward (gradients in the order before the last cell build)."""
+    for t in (rho_bar, xb, yb, zb):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != cfg.n:
+            raise ValueError("density_backward takes contiguous FP64 tensors of length n")
+    ps = parts.c()
+    _check(lib().sph_density_backward(C.byref(cfg.c()), C.byref(ps), ws.ptr, aws.ptr,
+                                      C.c_void_p(rho_bar.data_ptr()), C.c_void_p(xb.data_ptr()),
+                                      C.c_void_p(yb.data_ptr()), C.c_void_p(zb.data_ptr()),
+                                      _stream(stream)), "sph_density_backward")
+
+
+SNAP_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",
+               "p_ref", "rho_ref", "id")
+
+
+def snapshot(parts: Particles, g: Globals) -> dict:
+    """Device copy of the state arrays and the globals (a step checkpoint)."""
+    snap = {k: parts.t[k].clone() for k in SNAP_FIELDS if k in parts.t}
+    snap["_globals"] = g.t.clone()
+    return snap
+
+
+def restore(parts: Particles, g: Globals, snap: dict):
+    for k, v in snap.items():
+        if k == "_globals":
+            g.t.copy_(v)
+        else:
+            parts.t[k].copy_(v)
+
+
+def density_eval(cfg: Config, parts: Particles, ws: Workspace, stream=None):
+    """Cell build, h update, lists and density of the current state (the
+    rollout's final density evaluation)."""
+    build_cells(cfg, parts, ws, stream)
+    update_h(cfg, parts, ws, stream)
+    find_neighbors(cfg, parts, ws, stream)
+    density(cfg, parts, ws, stream)
+
+
+class Rollout:
+    """`steps` forward steps from an initial state with checkpoints every `ckpt`
+    steps, then a density evaluation; reverse mode by segments (restore the
+    segment's checkpoint, re-run its steps to recover each step's input state,
+    then sph_step_backward in reverse order).  The structure (h, dt, lists, AV
+    branches) of each step is frozen: the replays reproduce it bit for bit.
+
+    Particles keep their ids; inputs and outputs of the differentiable map are
+    keyed by id, in id order."""
+
+    def __init__(self, cfg: Config, parts: Particles, g: Globals, ws: Workspace,
+                 steps: int, ckpt: int, aws: AdjointWorkspace = None):
+        if cfg.precision != FP64:
+            raise ValueError("the adjoint rollout is FP64")
+        if steps < 1 or ckpt < 1:
+            raise ValueError("steps and ckpt must be >= 1")
+        self.cfg, self.parts, self.g, self.ws = cfg, parts, g, ws
+        self.steps, self.ckpt = steps, ckpt
+        self.aws = aws or AdjointWorkspace(cfg)
+        self.initial = snapshot(parts, g)
+        self.snaps = {}
+        self.final = None
+
+    def set_velocity(self, v0: torch.Tensor):
+        """Sets v and v^{n-1/2} of the initial state from v0 (n, 3), keyed by id."""
+        idx = self.initial["id"]
+        v = v0.to(torch.float64)[idx]
+        for k, col in (("vx", 0), ("vy", 1), ("vz", 2)):
+            self.initial[k].copy_(v[:, col])
+            self.initial["vh" + k[1]].copy_(v[:, col])
+
+    def forward(self) -> torch.Tensor:
+        """Runs the rollout; returns the final density keyed by id."""
+        cfg, parts, g, ws = self.cfg, self.parts, self.g, self.ws
+        restore(parts, g, self.initial)
+        self.snaps = {}
+        for k in range(self.steps):
+            if k % self.ckpt == 0:
+                self.snaps[k] = snapshot(parts, g)
+            step(cfg, parts, g, ws)
+        self.final = snapshot(parts, g)
+        density_eval(cfg, parts, ws)
+        rho = torch.empty_like(parts["rho"])
+        rho[parts["id"]] = parts["rho"]
+        return rho
+
+    def backward(self, rho_bar: torch.Tensor) -> Grads:
+        """Gradient of <rho_bar, rho_final> with respect to the initial state,
+        per slot of the initial order (a Grads)."""
+        cfg, parts, g, ws, aws = self.cfg, self.parts, self.g, self.ws, self.aws
+        n = cfg.n
+        dev = parts["x"].device
+        restore(parts, g, self.final)
+        density_eval(cfg, parts, ws)
+        rb = rho_bar.to(torch.float64)[parts["id"]].contiguous()
+        gout, gin = Grads(n, dev), Grads(n, dev)
+        density_backward(cfg, parts, ws, aws, rb, gout["x"], gout["y"], gout["z"])
+        for s0 in reversed(range(0, self.steps, self.ckpt)):
+            s1 = min(s0 + self.ckpt, self.steps)
+            restore(parts, g, self.snaps[s0])
+            inputs = [self.snaps[s0]]
+            for k in range(s0, s1 - 1):
+                step(cfg, parts, g, ws)
+                inputs.append(snapshot(parts, g))
+            for k in reversed(range(s0, s1)):
+                restore(parts, g, inputs[k - s0])
+                step_backward(cfg, parts, g, ws, aws, gout, gin)
+                gout, gin = gin, gout
+        return gout
+
+    def velocity_grad(self, grads: Grads) -> torch.Tensor:
+        """d/dv0 (keyed by id, (n, 3)) from the initial-state gradient: v0 sets
+        both v and v^{n-1/2} of the initial state."""
+        idx = self.initial["id"]
+        out = torch.zeros((self.cfg.n, 3), dtype=torch.float64, device=idx.device)
+        for col, a in enumerate("xyz"):
+            out[idx, col] = grads["v" + a] + grads["vh" + a]
+        return out
+
+
+class DensityRollout(torch.autograd.Function):
+    """rho_final(v0) of a Rollout as a differentiable torch function of the
+    initial velocities v0 (n, 3), both keyed by particle id."""
+
+    @staticmethod
+    def forward(ctx, v0, rollout: Rollout):
+        rollout.set_velocity(v0.detach())
+        ctx.rollout = rollout
+        return rollout.forward()
+
+    @staticmethod
+    def backward(ctx, rho_bar):
+        r = ctx.rollout
+        return r.velocity_grad(r.backward(rho_bar.contiguous())), None
