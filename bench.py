@@ -54,16 +54,19 @@ FLOPS_PER_PAIR = {
 }
 
 
-def bytes_per_particle(phase, k_g, k_s, wc):
+def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2):
     """Algorithmic HBM bytes per particle of one phase of sph_step."""
     return {
         # bbox (x y z h), keys, 8 radix passes over 8-byte keys and 4-byte indices,
         # permutation of the state (15 fields with the weakly compressible EOS,
         # else 13, plus the id), cell table fill
         "build_cells": 32 + 12 + 8 * 24 + (16 if wc else 14) * 16 + 32 + 8,
-        "candidates": 32 + 4,                         # p4 read, count write (+ lists below)
-        "newton_h": 32 + 8,                           # p4 read, h write (+ lists below)
-        "lists": 64 + 8 + 4 * k_s,                    # p4 repack, counts, filtered list
+        # p4 read, candidate list and count written (k_c candidates per particle)
+        "candidates": 32 + 4 + 4 * k_c,
+        # p4 read, candidate list read once per iteration, h written
+        "newton_h": 32 + 8 + 4 * k_c * iters,
+        # p4 repack, candidates read, counts and the filtered list written
+        "lists": 64 + 4 + 4 * k_c + 8 + 4 * k_s,
         "density": (100 if wc else 84) + 4 * k_g,     # p4 m u (p_ref rho_ref), out 4 fields
         "iad": 24 + 32 + 72 + 4 + 4 * k_g + 48 + 128,  # vol, p4, rec sources, list, C, records
         "momentum_energy": 32 + 128 + 8 + 8 + 4 * k_s + 32,  # p4, record, u, counts, list, out
@@ -94,13 +97,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roofline(phases, n, k_g, k_s, wc, iters):
+def roofline(phases, n, k_g, k_s, wc, iters, k_c):
     """Roofline of the phase that takes the longest.  Both ceilings are evaluated
     (algorithmic HBM bytes against 8 TB/s, algorithmic FP64 flops against the
     78.6 TFLOP/s vector peak); the binding one (larger fraction) is reported."""
     dom = max(phases, key=phases.get)
     t = phases[dom] * 1e-3
-    by = bytes_per_particle(dom, k_g, k_s, wc)
+    by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters)
     hbm = by * n / t / 1e9
     res = {"kernel": dom, "phase_ms": phases[dom], "traffic": None}
     pairs = {"newton_h": None, "density": k_g * n, "iad": k_g * n, "momentum_energy": k_s * n}
@@ -251,8 +254,14 @@ def main():
                    "newton_iters": cfg.newton_iters},
         "phase_ms": {k: round(v, 4) for k, v in phases.items()},
     }
-    out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters)
-    step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc) for k in phases) * n
+    k_c = 0.0
+    if cfg.h_ratio_max <= 1.25:
+        nk, _ = sph.candidates_view(cfg, ws)
+        k_c = float(nk.double().mean())
+        out["config"]["candidates_mean"] = k_c
+    out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters, k_c)
+    step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters)
+                     for k in phases) * n
     out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     if not args.no_mixed and prec == sph.FP64:

@@ -268,6 +268,12 @@ sph_status sph_density_backward(const sph_config* cfg, const sph_particles* p, v
 sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,
                               const int32_t** ns, const int32_t** list, int32_t* capacity);
 
+/* (host) Device pointers into ws after sph_step with h_ratio_max <= 1.25 (the
+ * fused path): nk (int32[n]), each slot's true candidate count (pairs within
+ * 2*h_ratio_max*max(h0_a, h0_b)), and the candidate capacity per slot. */
+sph_status sph_candidates_view(const sph_config* cfg, void* ws, const int32_t** nk,
+                               int32_t* capacity);
+
 /* (host) Device pointers into ws after sph_build_cells: the sorted keys
  * (uint64[n]) and the permutation perm (uint32[n], slot -> slot before the call). */
 sph_status sph_order_view(const sph_config* cfg, void* ws, const uint64_t** keys,

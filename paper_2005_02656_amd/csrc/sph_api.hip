@@ -457,6 +457,18 @@ sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** n
     return SPH_OK;
 }
 
+sph_status sph_candidates_view(const sph_config* cfg, void* ws, const int32_t** nk,
+                               int32_t* capacity)
+{
+    if (!config_ok(cfg)) return SPH_E_ARG;
+    if (!ws || ((uintptr_t)ws & 255)) return SPH_E_WORKSPACE;
+    Layout L = make_layout(cfg->n, cfg->ng_max);
+    Ws W = carve(ws, L);
+    if (nk) *nk = W.nk;
+    if (capacity) *capacity = L.cand_cap;
+    return SPH_OK;
+}
+
 sph_status sph_order_view(const sph_config* cfg, void* ws, const uint64_t** keys,
                           const uint32_t** perm)
 {

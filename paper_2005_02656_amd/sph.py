@@ -132,6 +132,7 @@ _SIGS = {
     "sph_neighbors_view": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
     "sph_order_view": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_candidates_view": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sph_status_sync": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sph_step_marked": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_int32]),
@@ -338,6 +339,15 @@ def neighbors_view(cfg: Config, ws: Workspace):
     tiles = (n + 63) // 64
     return (ws.view(nc.value, n, torch.int32), ws.view(ns.value, n, torch.int32),
             ws.view(lst.value, tiles * cap.value * 64, torch.int32).view(tiles, cap.value, 64))
+
+
+def candidates_view(cfg: Config, ws: Workspace):
+    """Returns (nk int32 view, capacity): true candidate counts of the fused step."""
+    nk = C.c_void_p()
+    cap = C.c_int32()
+    _check(lib().sph_candidates_view(C.byref(cfg.c()), ws.ptr, C.byref(nk), C.byref(cap)),
+           "sph_candidates_view")
+    return ws.view(nk.value, cfg.n, torch.int32), cap.value
 
 
 def order_view(cfg: Config, ws: Workspace):

@@ -5,10 +5,10 @@ by test_oracle_adjoint.py).
 
 The oracle takes its frozen structure (Newton h, dt) from the C oracle, never
 from the GPU.  Gradients are compared field by field relative to the field's
-largest entry.  Bar: 1e-11 for one step and the density (both sides are FP64;
-the residual is summation order and the 1e-16-level differences between the
-GPU's and the oracle's own h and dt), 1e-9 for a multi-step rollout (the
-Jacobian product of several steps amplifies those differences)."""
+largest entry.  Bar: 1e-12, the FP64 field bar, for one step, the density and a
+3-step rollout (both sides are FP64; the residual is summation order and the
+1e-16-level differences between the GPU's and the oracle's own h and dt; the
+measured errors are below 1e-13)."""
 import numpy as np
 import pytest
 import torch
@@ -19,8 +19,8 @@ from paper_2005_02656_amd import inputs, sph
 from gpu_support import Run, configs, rel_err
 
 pytestmark = pytest.mark.gpu
-TOL_STEP = 1e-11
-TOL_ROLLOUT = 1e-9
+TOL_STEP = 1e-12
+TOL_ROLLOUT = 1e-12
 NG = 400
 
 
@@ -91,10 +91,11 @@ def test_step_backward_matches_oracle(name):
          + (T["vhz"] * out["vh"][:, 2]).sum() + (T["u"] * out["u"]).sum()
          + (T["du_m1"] * out["du_m1"]).sum())
     L.backward()
-    ref = {"x": ts["x"].grad[:, 0], "y": ts["x"].grad[:, 1], "z": ts["x"].grad[:, 2],
-           "vx": ts["v"].grad[:, 0], "vy": ts["v"].grad[:, 1], "vz": ts["v"].grad[:, 2],
-           "vhx": ts["vh"].grad[:, 0], "vhy": ts["vh"].grad[:, 1], "vhz": ts["vh"].grad[:, 2],
-           "u": ts["u"].grad, "du_m1": ts["du_m1"].grad}
+    col = lambda g, c: None if g is None else g[:, c]
+    ref = {"x": col(ts["x"].grad, 0), "y": col(ts["x"].grad, 1), "z": col(ts["x"].grad, 2),
+           "vx": col(ts["v"].grad, 0), "vy": col(ts["v"].grad, 1), "vz": col(ts["v"].grad, 2),
+           "vhx": col(ts["vh"].grad, 0), "vhy": col(ts["vh"].grad, 1),
+           "vhz": col(ts["vh"].grad, 2), "u": ts["u"].grad, "du_m1": ts["du_m1"].grad}
     # GPU: a forward step tells the output slot order; the backward replays the
     # step from the same input state
     probe = Run(w, cfg, a)
@@ -113,7 +114,10 @@ def test_step_backward_matches_oracle(name):
     assert np.array_equal(r.ids(), out_ids)
     errs = {}
     for k in sph.GRAD_FIELDS:
-        errs[k] = rel_err(gin[k].cpu().numpy(), ref[k].numpy())
+        # torch leaves the gradient of an input that reaches no output (du_m1 on
+        # a first step) at None: it is zero
+        o = ref[k].numpy() if ref[k] is not None else np.zeros(n)
+        errs[k] = rel_err(gin[k].cpu().numpy(), o)
     print(name, "dt", gl["dt"], {k: f"{v:.1e}" for k, v in errs.items()})
     for k, e in errs.items():
         assert e <= TOL_STEP, (k, e)
