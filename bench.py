@@ -270,15 +270,20 @@ def main():
         torch.cuda.synchronize()
         e0.record(stream)
         for i in range(args.steps):
-            sph.step(mcfg, parts, g, ws)
+            sph.step_marked(mcfg, parts, g, ws, marks[i])
         e1.record(stream)
         torch.cuda.synchronize()
         mms = e0.elapsed_time(e1) / args.steps
+        mph = {k: 0.0 for k in sph.STEP_PHASES}
+        for mk in marks:
+            for k, v in mk.phase_ms().items():
+                mph[k] += v / args.steps
         st, bits = sph.status_sync(ws)
         if st:
             raise RuntimeError(f"mixed steps raised {sph.status_string(st)} (bits {bits})")
         out["mixed"] = {"ms_per_step": mms, "value": n / (mms * 1e-3),
                         "speedup_vs_fp64": ms / mms,
+                        "phase_ms": {k: round(v, 4) for k, v in mph.items()},
                         "note": "same workload and state, FP32 pair terms with FP64 sums"}
         log(f"[bench] mixed precision: {mms:.3f} ms/step")
     del parts, ws

@@ -437,9 +437,15 @@ void ora_momentum_energy(const ora_config* cf, int64_t n, const double* x, const
             double vg = vab[0] * g[0] + vab[1] * g[1] + vab[2] * g[2];
             e1 += m[b] * vA;
             e2 += vg;
-            sa += sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]) +
-                  sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-            se += fabs(pa * m[b] * vA) + fabs(0.5 * vg);
+            /* error scales: sums of the norms of the terms; for du the dot
+               products are bounded by the products of the norms, since they
+               cancel (to rounding) whenever v_ab is orthogonal to x_ab */
+            double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+            double ng = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+            double nv = sqrt(vab[0] * vab[0] + vab[1] * vab[1] + vab[2] * vab[2]);
+            double nA = sqrt(Aa[0] * Aa[0] + Aa[1] * Aa[1] + Aa[2] * Aa[2]);
+            sa += nf + ng;
+            se += fabs(pa) * m[b] * nv * nA + 0.5 * nv * ng;
         }
         ax[a] = acc[0];
         ay[a] = acc[1];
