@@ -97,7 +97,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roofline(phases, n, k_g, k_s, wc, iters, k_c):
+# the kernel that does the work of each phase (its rocprofv3 name)
+PHASE_KERNEL = {"build_cells": "k_radix_scatter", "candidates": "k_candidates",
+                "newton_h": "k_update_h_list", "lists": "k_filter", "density": "k_density",
+                "iad": "k_iad", "momentum_energy": "k_momentum_energy",
+                "integrate": "k_integrate"}
+
+
+def traffic_from_profile(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary of this
+    workload, or None when there is none or the sources changed since."""
+    from paper_2005_02656_amd import profiling
+    s = profiling.read_summary(os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md"))
+    if not s or s.get("source_digest") != profiling.source_digest():
+        return None
+    try:
+        return float(s["fetch_bytes_per_launch"]) + float(s["write_bytes_per_launch"])
+    except KeyError:
+        return None
+
+
+def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload):
     """Roofline of the phase that takes the longest.  Both ceilings are evaluated
     (algorithmic HBM bytes against 8 TB/s, algorithmic FP64 flops against the
     78.6 TFLOP/s vector peak); the binding one (larger fraction) is reported."""
@@ -105,7 +125,9 @@ def roofline(phases, n, k_g, k_s, wc, iters, k_c):
     t = phases[dom] * 1e-3
     by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters)
     hbm = by * n / t / 1e9
-    res = {"kernel": dom, "phase_ms": phases[dom], "traffic": None}
+    kern = PHASE_KERNEL[dom]
+    res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom],
+           "traffic": traffic_from_profile(kern, workload)}
     pairs = {"newton_h": None, "density": k_g * n, "iad": k_g * n, "momentum_energy": k_s * n}
     if dom in FLOPS_PER_PAIR and pairs[dom] is not None:
         fl = FLOPS_PER_PAIR[dom] * pairs[dom]
@@ -259,7 +281,7 @@ def main():
         nk, _ = sph.candidates_view(cfg, ws)
         k_c = float(nk.double().mean())
         out["config"]["candidates_mean"] = k_c
-    out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters, k_c)
+    out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters, k_c, args.workload)
     step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters)
                      for k in phases) * n
     out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)

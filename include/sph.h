@@ -196,8 +196,9 @@ sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, voi
 /* sph_step with phase markers, for timing the step's kernels on its own stream.
  * Enqueues exactly the launches of sph_step and records events[k] (hipEvent_t
  * handles created by the caller, (host) array of SPH_STEP_PHASES + 1) after
- * phase k: 0 start; 1 cell build; 2 candidate walk (fused path; walk path:
- * the h update); 3 Newton h update (walk path: empty); 4 neighbour lists;
+ * phase k: 0 start; 1 cell build (and the per-cell h_max pass of the fused
+ * path); 2 candidate walk (walk path: the h update); 3 Newton h update (walk
+ * path: empty); 4 neighbour lists;
  * 5 density; 6 IAD; 7 momentum/energy and the time step; 8 integration and
  * sums.  Returns SPH_E_ARG if nevents differs or a handle is NULL. */
 #define SPH_STEP_PHASES 8

@@ -98,42 +98,37 @@ Adj carve_adj(void* base, int64_t n)
 }
 
 // ---------------------------------------------------------------- kernel derivatives
-// S = sinc^n and dS/dt at t = (pi/2)^2 v^2
+// value and t-derivative of a polynomial in t (Horner on both)
+template <int K>
+SPH_DEV void horner_d(const double (&c)[K], double t, double& p, double& dp)
+{
+    p = c[K - 1];
+    dp = 0.0;
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) {
+        dp = fma(dp, t, p);
+        p = fma(p, t, c[k]);
+    }
+}
+
+// S = sinc^n and dS/dt at t = (pi/2)^2 v^2 (the forward's polynomial for sinc)
 SPH_DEV void sinc_dt(double t, int n, double& S, double& dS)
 {
-    double s = kSinc.s[kSincTerms - 1];
-    double ds = (kSincTerms - 1) * kSinc.s[kSincTerms - 1];
-#pragma unroll
-    for (int k = kSincTerms - 2; k >= 1; --k) {
-        s = fma(s, t, kSinc.s[k]);
-        ds = fma(ds, t, k * kSinc.s[k]);
-    }
-    s = fma(s, t, kSinc.s[0]);
+    double s, ds;
+    horner_d(kSincS64, t, s, ds);
     const double p = pow_nm1(s, n);   // s^(n-1)
     S = p * s;
     dS = (double)n * p * ds;
 }
 
-// dS/dt and dQ/dt, with Q = v dS/dv = n s^(n-1) q, q = x sinc'(x) (power series in t)
+// dS/dt and dQ/dt, with Q = v dS/dv = n s^(n-1) q and q = x sinc'(x) = t qt(t)
 SPH_DEV void sinc_dt2(double t, int n, double& dS, double& dQ)
 {
-    double s = kSinc.s[kSincTerms - 1];
-    double ds = (kSincTerms - 1) * kSinc.s[kSincTerms - 1];
-#pragma unroll
-    for (int k = kSincTerms - 2; k >= 1; --k) {
-        s = fma(s, t, kSinc.s[k]);
-        ds = fma(ds, t, k * kSinc.s[k]);
-    }
-    s = fma(s, t, kSinc.s[0]);
-    // q/t = sum_k d_k t^k (k = 0 .. kSincTerms-2), dq/dt = sum_k (k+1) d_k t^k
-    double qt = kSinc.d[kSincTerms - 2];
-    double dq = (kSincTerms - 1) * kSinc.d[kSincTerms - 2];
-#pragma unroll
-    for (int k = kSincTerms - 3; k >= 0; --k) {
-        qt = fma(qt, t, kSinc.d[k]);
-        dq = fma(dq, t, (k + 1) * kSinc.d[k]);
-    }
+    double s, ds, qt, dqt;
+    horner_d(kSincS64, t, s, ds);
+    horner_d(kSincQ64, t, qt, dqt);
     const double q = qt * t;
+    const double dq = qt + t * dqt;
     double p2 = 1.0;   // s^(n-2)
     for (int i = 2; i < n; ++i) p2 = p2 * s;
     const double p1 = p2 * s;   // s^(n-1)

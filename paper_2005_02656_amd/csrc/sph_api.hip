@@ -340,8 +340,10 @@ sph_status step_rates(Ctx& c, sph_particles* p, sph_globals* g, const Marks& mk 
     // feeds both the Newton iterations and the lists (fused), else the walks of
     // the stage entry points run; the IAD pass writes the momentum records
     if (c.P.cand_cap > 0) {
+        // the fused launcher re-records event 1 after its cell h_max pass, so
+        // that phase 2 holds the candidate walk alone
         Marks sub;
-        if (mk.ev && mk.n > 2) sub = Marks{mk.ev + 2, mk.n - 2};
+        if (mk.ev && mk.n > 1) sub = Marks{mk.ev + 1, mk.n - 1};
         if ((e = launch_fused_h_lists(c.P, c.L, c.W, p, c.s, sub))) return SPH_E_HIP;
     } else {
         if ((e = launch_update_h(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;

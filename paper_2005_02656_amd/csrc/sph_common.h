@@ -58,6 +58,7 @@ struct Domain {
     uint64_t dtmin_bits;       // min_a h_a/c_a (bits of a positive double)
     int32_t level, shift, ncell_axis;
     uint32_t err;              // sticky SPH_ERRBIT_* word
+    uint32_t refit;            // fused step: an h left the short candidate reach
     int64_t built_n;
 };
 
@@ -88,11 +89,30 @@ __host__ __device__ inline int64_t lpos(int64_t a, int j, int cap)
     return ((a >> 6) * (int64_t)cap + j) * 64 + (a & 63);
 }
 
+// Candidate lists (fused step) are stored in chunks of 8 entries per slot: the
+// 8 entries j..j+7 (j a multiple of 8) of slot a are 32 contiguous bytes, and
+// the 64 slots of a wavefront tile keep their chunks side by side.  The walk
+// appends into registers and writes whole chunks (the writes are not lane-
+// synchronous, so one 4-byte write per entry left lines partly written); the
+// readers load one chunk per batch of 8.  cap is a multiple of 8.
+__host__ __device__ inline int64_t lpos8(int64_t a, int j, int cap)
+{
+    return (((a >> 6) * (int64_t)(cap >> 3) + (j >> 3)) * 64 + (a & 63)) * 8 + (j & 7);
+}
+
 // The fused step walks the cells once for a candidate list with reach
 // 2 kappa max(h0_a, h0_b): the Newton clamp keeps h <= kappa h0, so every set
 // the step needs is a subset.  Used when kappa <= kFusedKappaMax; the
 // workspace layout depends on (n, ng_max) only, never on per-call parameters.
 constexpr double kFusedKappaMax = 1.25;
+// The fused step first collects candidates within 2 lambda max(h0_a, h0_b),
+// lambda = kFusedReach (1.16x the list volume instead of kappa^3 = 1.95x), and
+// runs Newton on them; if any iterate h leaves [0, lambda h0] it repeats both
+// with the full reach kappa.  Either way the sets are exact.
+#ifndef SPH_FUSED_REACH
+#define SPH_FUSED_REACH 1.05
+#endif
+constexpr double kFusedReach = SPH_FUSED_REACH;
 int candidate_capacity(int ng_max);
 
 // ---------------------------------------------------------------- workspace layout
@@ -190,31 +210,27 @@ SPH_DEV double disp(const Params& P, double xa, double ya, double za, double xb,
 }
 
 // ------------------------------------------------------------- sinc kernel
-// With x = (pi/2) v and t = x^2 the kernel needs only even power series in t:
-//   sinc(x)          = sum_{k>=0} (-1)^k t^k / (2k+1)!
-//   x sinc'(x)       = cos x - sinc x = sum_{k>=1} (-1)^k 2k t^k / (2k+1)!
-// (Taylor series; 16 terms reach double precision on 0 <= x <= pi since
-// pi^30/31! < 1e-18).  No sqrt, sin or division per pair.
-constexpr int kSincTerms = 16;
-struct SincTable {
-    double s[kSincTerms];   // coefficient of t^k in sinc
-    double d[kSincTerms];   // coefficient of t^(k+1) in x sinc'(x)
-    constexpr SincTable() : s(), d()
-    {
-        double c = 1.0;  // (-1)^k / (2k+1)!
-        for (int k = 0; k < kSincTerms; ++k) {
-            if (k > 0) c = -c / ((2.0 * k) * (2.0 * k + 1.0));
-            s[k] = c;
-        }
-        // coefficient of t^(k+1) in x sinc'(x) is 2(k+1) times that of t^(k+1) in sinc
-        for (int k = 0; k + 1 < kSincTerms; ++k) d[k] = 2.0 * (k + 1) * s[k + 1];
-        d[kSincTerms - 1] = 0.0;
-    }
-};
-constexpr SincTable kSinc{};
+// With x = (pi/2) v and t = x^2 the kernel needs only even functions of x,
+// i.e. functions of t on 0 <= t <= pi^2:
+//   sinc(x)      ~ kSincS64 polynomial in t (11 terms)
+//   x sinc'(x)   ~ t * kSincQ64 polynomial in t (10 terms)
+// (fits on the support, accurate to the rounding of their Horner evaluation,
+// generated by gen_sinc_poly.py).  No sin, sqrt or division per pair.
+}  // namespace sph
+#include "sph_sinc_poly.h"
+namespace sph {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kPiHalfSq = (kPi * kPi) / 4.0;
+
+template <int K>
+SPH_DEV double horner(const double (&c)[K], double t)
+{
+    double s = c[K - 1];
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) s = fma(s, t, c[k]);
+    return s;
+}
 
 // s^(n-1) for the integer exponent n (n is uniform across the launch; the usual
 // n = 6 takes three multiplications)
@@ -233,25 +249,33 @@ SPH_DEV T pow_nm1(T s, int n)
 // S_n and v dS_n/dv at t = (pi/2)^2 v^2, integer n >= 1
 SPH_DEV void sinc_terms(double t, int n, double& S, double& vdS)
 {
-    double s = kSinc.s[kSincTerms - 1];
-#pragma unroll
-    for (int k = kSincTerms - 2; k >= 0; --k) s = fma(s, t, kSinc.s[k]);
-    double q = kSinc.d[kSincTerms - 2];
-#pragma unroll
-    for (int k = kSincTerms - 3; k >= 0; --k) q = fma(q, t, kSinc.d[k]);
-    q = q * t;                      // x sinc'(x)
-    const double p = pow_nm1(s, n); // s^(n-1)
+    const double s = horner(kSincS64, t);
+    const double q = horner(kSincQ64, t) * t;   // x sinc'(x)
+    const double p = pow_nm1(s, n);             // s^(n-1)
     S = p * s;
     vdS = (double)n * p * q;
 }
 
 SPH_DEV double sinc_S(double t, int n)
 {
-    double s = kSinc.s[kSincTerms - 1];
-#pragma unroll
-    for (int k = kSincTerms - 2; k >= 0; --k) s = fma(s, t, kSinc.s[k]);
+    const double s = horner(kSincS64, t);
     return pow_nm1(s, n) * s;
 }
+
+// Largest number of wavefronts per SIMD for the neighbour-loop kernels (0: as
+// many as the registers allow).  These kernels gather neighbour records that
+// the wavefronts of a compute unit do not share, so past a point more resident
+// wavefronts only evict each other's records from the caches.
+#define SPH_WAVES_CAP(n) __attribute__((amdgpu_waves_per_eu(1, n)))
+#ifndef SPH_WAVES_MOM
+#define SPH_WAVES_MOM 2
+#endif
+#ifndef SPH_WAVES_PAIR
+#define SPH_WAVES_PAIR 2
+#endif
+#ifndef SPH_WAVES_SEARCH
+#define SPH_WAVES_SEARCH 3
+#endif
 
 // neighbour loops load this many neighbours' records before computing on them
 // (independent gathers in flight per wavefront)

@@ -17,7 +17,6 @@
 namespace sph {
 namespace {
 
-constexpr int kSincTermsF = 10;   // FP32: pi^20/21! < 2e-10
 
 struct alignas(16) PosM {
     float ox, oy, oz;     // offset from the cell origin
@@ -69,29 +68,29 @@ __device__ __forceinline__ float disp_m(const CellGeom& g, const PosM& a, const 
     return (dx * dx + dy * dy) + dz * dz;
 }
 
+template <int K>
+__device__ __forceinline__ float horner_f(const float (&c)[K], float t)
+{
+    float s = c[K - 1];
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) s = fmaf(s, t, c[k]);
+    return s;
+}
+
+// FP32 S_n and v dS_n/dv from the FP32 fits of sinc and x sinc'(x) / t
 __device__ __forceinline__ void sinc_terms_f(float t, int n, float& S, float& vdS)
 {
-    float s = (float)kSinc.s[kSincTermsF - 1];
-#pragma unroll
-    for (int k = kSincTermsF - 2; k >= 0; --k) s = fmaf(s, t, (float)kSinc.s[k]);
-    float q = (float)kSinc.d[kSincTermsF - 2];
-#pragma unroll
-    for (int k = kSincTermsF - 3; k >= 0; --k) q = fmaf(q, t, (float)kSinc.d[k]);
-    q = q * t;
-    float p = 1.0f;
-    for (int i = 1; i < n; ++i) p = p * s;
+    const float s = horner_f(kSincS32, t);
+    const float q = horner_f(kSincQ32, t) * t;
+    const float p = pow_nm1(s, n);
     S = p * s;
     vdS = (float)n * p * q;
 }
 
 __device__ __forceinline__ float sinc_S_f(float t, int n)
 {
-    float s = (float)kSinc.s[kSincTermsF - 1];
-#pragma unroll
-    for (int k = kSincTermsF - 2; k >= 0; --k) s = fmaf(s, t, (float)kSinc.s[k]);
-    float p = s;
-    for (int i = 1; i < n; ++i) p = p * s;
-    return p;
+    const float s = horner_f(kSincS32, t);
+    return pow_nm1(s, n) * s;
 }
 
 // positions as cell index + FP32 offset, and FP32 masses

@@ -10,10 +10,15 @@
 // on floating-point values.
 #include "sph_common.h"
 
+// neighbours whose records the momentum/energy loop loads before computing
+#ifndef SPH_MOM_BATCH
+#define SPH_MOM_BATCH 2
+#endif
+
 namespace sph {
 namespace {
 
-__global__ __launch_bounds__(kBlock) void k_density(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_density(Params P, Domain* __restrict__ dom,
                                                     const int32_t* __restrict__ nc,
                                                     const int32_t* __restrict__ list,
                                                     const Pos4* __restrict__ p4,
@@ -113,7 +118,7 @@ __device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, double c1
     return q;
 }
 
-__global__ __launch_bounds__(kBlock) void k_iad(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_iad(Params P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ list,
                                                 const Pos4* __restrict__ p4,
@@ -202,7 +207,7 @@ struct MomOut {
 
 __global__ void k_dtmin_begin(Domain* d) { d->dtmin_bits = ord_bits(INFINITY); }
 
-__global__ __launch_bounds__(kBlock) void k_momentum_energy(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MOM) void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
                                                             const int32_t* __restrict__ list,
@@ -230,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_energy(Params P, Domain* __
         const int co = min(ns[a] - nc[a], ng);
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
-        constexpr int kMomBatch = 2;
+        constexpr int kMomBatch = SPH_MOM_BATCH;
         for (int k0 = 0; k0 < total; k0 += kMomBatch) {
             int32_t bb[kMomBatch];
             bool ok[kMomBatch], gat[kMomBatch];

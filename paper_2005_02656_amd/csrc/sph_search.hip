@@ -215,7 +215,11 @@ __global__ __launch_bounds__(kBlock) void k_update_h(Params P, const Domain* __r
     h[a] = hc;
 }
 
-__global__ void k_hmax_begin(Domain* d) { d->hmax_new_bits = ord_bits(0.0); }
+__global__ void k_hmax_begin(Domain* d)
+{
+    d->hmax_new_bits = ord_bits(0.0);
+    d->refit = 0u;
+}
 
 // largest h per cell (for the symmetric search) and overall
 __global__ __launch_bounds__(kBlock) void k_cells_hmax(Params P, Domain* __restrict__ dom,
@@ -286,16 +290,18 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 }
 
 // ---------------------------------------------------------------- fused step
-// Candidates: b != a with r^2 < (2 kappa max(h0_a, h0_b))^2, by the same
-// per-target cell walk.  (A wavefront walking the union of its 64 targets'
+// Candidates: b != a with r^2 < (2 kap max(h0_a, h0_b))^2 (kap: the reach
+// factor of this pass), by the same per-target cell walk.  (A wavefront walking the union of its 64 targets'
 // stencils, with scalar or LDS-staged particle loads, tested 2.4x more pairs
 // and ran 1.6-2.1x slower at 64 M particles.)
-__global__ __launch_bounds__(kBlock) void k_candidates(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_candidates(Params P, Domain* __restrict__ dom,
                                                        const CellRange* __restrict__ cells,
                                                        const Pos4* __restrict__ p4,
                                                        int32_t* __restrict__ nk,
-                                                       int32_t* __restrict__ cand)
+                                                       int32_t* __restrict__ cand,
+                                                       double kap, int only_if_refit)
 {
+    if (only_if_refit && dom->refit == 0u) return;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
@@ -304,10 +310,15 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Params P, Domain* __restr
     const Domain D = *dom;
     const Pos4 pa = p4[a];
     const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
-    const double kap = P.kappa;
     const double hmax0 = ord_value(D.hmax_new_bits);
     const int cap = P.cand_cap;
     int k = 0;
+    int32_t buf[8];
+    auto flush = [&](int j0) {
+        int4* dst = (int4*)(cand + lpos8(a, j0, cap));
+        dst[0] = make_int4(buf[0], buf[1], buf[2], buf[3]);
+        dst[1] = make_int4(buf[4], buf[5], buf[6], buf[7]);
+    };
     walk_cells(
         P, D, cells, p4, xa, ya, za, 2.0 * kap * fmax(ha, hmax0),
         [&](const CellRange& cr, double g2) {
@@ -320,21 +331,38 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Params P, Domain* __restr
             double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
             double R = 2.0 * kap * fmax(ha, q.h);
             if (r2 < R * R) {
-                if (k < cap) cand[lpos(a, k, cap)] = b;
+                if (k < cap) {
+                    buf[k & 7] = b;
+                    if ((k & 7) == 7) flush(k & ~7);
+                }
                 ++k;
             }
         });
+    if (k < cap && (k & 7) != 0) flush(k & ~7);   // the partial last chunk
     nk[a] = k;
     if (k > cap) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
 }
 
+// one chunk of 8 candidates of slot a (entries at or past cnt read as a itself)
+__device__ __forceinline__ void load_chunk(const int32_t* __restrict__ cand, int64_t a, int j0,
+                                           int cap, int cnt, int32_t bb[8])
+{
+    const int4* src = (const int4*)(cand + lpos8(a, j0, cap));
+    const int4 lo = src[0], hi = src[1];
+    const int32_t v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bb[u] = (j0 + u < cnt) ? v[u] : (int32_t)a;
+}
+
 // Newton iterations summing over the candidate list (self term added: S(0) = 1)
-__global__ __launch_bounds__(kBlock) void k_update_h_list(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_update_h_list(Params P, Domain* __restrict__ dom,
                                                           const int32_t* __restrict__ nk,
                                                           const int32_t* __restrict__ cand,
                                                           const Pos4* __restrict__ p4,
-                                                          double* __restrict__ h)
+                                                          double* __restrict__ h, double lam,
+                                                          int only_if_refit)
 {
+    if (only_if_refit && dom->refit == 0u) return;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
@@ -345,25 +373,27 @@ __global__ __launch_bounds__(kBlock) void k_update_h_list(Params P, Domain* __re
     const double h0 = pa.h;
     const int cap = P.cand_cap;
     const int cnt = min(nk[a], cap);
+    // the candidates reach 2 lam max(h0_a, h0_b): exact as long as every
+    // iterate stays at or below lam h0 (2 (lam h0) == (2 lam) h0 in FP64)
+    const double hlim = lam * h0;
+    bool over = false;
     double hc = h0;
     for (int it = 0; it < P.newton_iters; ++it) {
         const double h2 = 2.0 * hc;
         const double R2 = h2 * h2;
         const double tsc = kPiHalfSq / (hc * hc);
         double sS = 1.0, sV = 0.0;
-        for (int j0 = 0; j0 < cnt; j0 += kBatch) {
-            int32_t bb[kBatch];
+        for (int j0 = 0; j0 < cnt; j0 += 8) {
+            int32_t bb[8];
+            load_chunk(cand, a, j0, cap, cnt, bb);
+            double qx[8], qy[8], qz[8];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u)
-                bb[u] = (j0 + u < cnt) ? cand[lpos(a, j0 + u, cap)] : (int32_t)a;
-            double qx[kBatch], qy[kBatch], qz[kBatch];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const Pos4* q = p4 + bb[u];
                 qx[u] = q->x; qy[u] = q->y; qz[u] = q->z;
             }
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 double dx, dy, dz;
                 double r2 = disp(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
                 if (j0 + u < cnt && r2 < R2) {
@@ -375,13 +405,19 @@ __global__ __launch_bounds__(kBlock) void k_update_h_list(Params P, Domain* __re
             }
         }
         hc = newton_step(P, hc, h0, sS, sV);
+        over = over || hc > hlim;
     }
     h[a] = hc;
-    check_cell_range(P, dom, hc);
+    if (over) {
+        // this h may have missed candidates; the full-reach pass recomputes it
+        atomicOr(&dom->refit, 1u);
+    } else {
+        check_cell_range(P, dom, hc);
+    }
 }
 
 // exact lists from the candidates with the final h (same layout as k_find_neighbors)
-__global__ __launch_bounds__(kBlock) void k_filter(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_filter(Params P, Domain* __restrict__ dom,
                                                    const int32_t* __restrict__ nk,
                                                    const int32_t* __restrict__ cand,
                                                    const Pos4* __restrict__ p4,
@@ -402,16 +438,14 @@ __global__ __launch_bounds__(kBlock) void k_filter(Params P, Domain* __restrict_
     const int cnt = min(nk[a], cap);
     const int ng = P.ng_max;
     int cg = 0, co = 0;
-    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
-        int32_t bb[kBatch];
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
+        int32_t bb[8];
+        load_chunk(cand, a, j0, cap, cnt, bb);
+        Pos4 q[8];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u)
-            bb[u] = (j0 + u < cnt) ? cand[lpos(a, j0 + u, cap)] : (int32_t)a;
-        Pos4 q[kBatch];
+        for (int u = 0; u < 8; ++u) q[u] = p4[bb[u]];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) q[u] = p4[bb[u]];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < 8; ++u) {
             if (j0 + u >= cnt) continue;
             const int32_t b = bb[u];
             double dx, dy, dz;
@@ -440,7 +474,7 @@ int candidate_capacity(int ng_max)
     // the candidate reach is at most kFusedKappaMax times the list reach:
     // kFusedKappaMax^3 times the volume, with 25% headroom
     double c = ng_max * kFusedKappaMax * kFusedKappaMax * kFusedKappaMax * 1.25;
-    int cap = (int)ceil(c);
+    int cap = ((int)ceil(c) + 7) & ~7;   // whole chunks of 8
     return cap > 8192 ? 8192 : cap;
 }
 
@@ -481,11 +515,23 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
     k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, L.ncells_cap);
-    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand);
     mk.at(0, s);
-    if (P.newton_iters > 0)
-        k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h);
+    // short reach first; the full-reach pair runs only if an h left it (the
+    // kernels read the device flag and return at once when it is clear)
+    const double lam = fmin(kFusedReach, P.kappa);
+    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand, lam, 0);
     mk.at(1, s);
+    if (P.newton_iters > 0) {
+        k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h, lam,
+                                                        0);
+        if (lam < P.kappa) {
+            k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand,
+                                                         P.kappa, 1);
+            k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h,
+                                                            P.kappa, 1);
+        }
+    }
+    mk.at(2, s);
     hipError_t e = launch_pack_p4(P, W, p, s);
     if (e != hipSuccess) return e;
     k_filter<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns, W.list);

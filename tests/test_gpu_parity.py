@@ -236,3 +236,25 @@ def test_step_deterministic():
                      ("x", "vx", "h", "rho", "ax", "du", "c11")} | {"g": r.g.t.cpu().numpy()})
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.parametrize("name", ["random", "lattice12"])
+def test_fused_step_short_reach(name):
+    """The fused step's h and lists are exact whether its short candidate reach
+    holds (lattice: h moves by far less than 5%) or its full-reach pass has to
+    run (random h in [0.06, 0.09]: Newton moves some h by more than 5%)."""
+    w = CASES[name]()
+    cfg, ocfg = configs(w, ng_max=NG)
+    a = w.arrays
+    if name == "random":
+        h1 = oracle.update_h(ocfg, a["x"], a["y"], a["z"], a["h"])
+        assert np.max(h1 / a["h"]) > 1.05          # the full-reach pass must run
+    r = Run(w, cfg)
+    sph.step(cfg, r.parts, r.g, r.ws)
+    assert r.status() == (0, 0)
+    h_o = oracle.update_h(ocfg, a["x"], a["y"], a["z"], a["h"])
+    assert rel_err(r.by_id("h"), h_o) < TOL
+    P, nc, ns = r.neighbor_pairs()
+    nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, a["x"], a["y"], a["z"], h_o)
+    assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
+    assert np.array_equal(P, oracle_pairs(lists, gath))
