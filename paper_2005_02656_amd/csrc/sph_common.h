@@ -276,6 +276,14 @@ SPH_DEV double sinc_S(double t, int n)
 #ifndef SPH_WAVES_SEARCH
 #define SPH_WAVES_SEARCH 3
 #endif
+#ifndef SPH_WAVES_MIXED
+#define SPH_WAVES_MIXED 2
+#endif
+
+// neighbours whose records the momentum/energy loops load before computing
+#ifndef SPH_MOM_BATCH
+#define SPH_MOM_BATCH 4
+#endif
 
 // neighbour loops load this many neighbours' records before computing on them
 // (independent gathers in flight per wavefront)

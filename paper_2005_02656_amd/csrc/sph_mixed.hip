@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_posm(Params P, const Domain* __
     mf[i] = (float)m[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_density_m(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_density_m(Params P, Domain* __restrict__ dom,
                                                       const int32_t* __restrict__ nc,
                                                       const int32_t* __restrict__ list,
                                                       const PosM* __restrict__ pm,
@@ -143,17 +143,32 @@ __global__ __launch_bounds__(kBlock) void k_density_m(Params P, Domain* __restri
     const float tsc = (float)(kPiHalfSq / (ha * ha));
     const int cnt = min(nc[a], P.ng_max);
     double sS = m[a], sD = 3.0 * m[a];
-#pragma unroll 2
-    for (int j = 0; j < cnt; ++j) {
-        int32_t b = list[lpos(a, j, P.ng_max)];
-        if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
-        float dx, dy, dz;
-        float r2 = disp_m(g, pa, pm[b], dx, dy, dz);
-        float S, vdS;
-        sinc_terms_f(r2 * tsc, P.sinc_n, S, vdS);
-        const float mb = mf[b];
-        sS += (double)(mb * S);
-        sD += (double)(mb * (3.0f * S + vdS));
+    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+        int32_t bb[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int32_t b = (j0 + u < cnt) ? list[lpos(a, j0 + u, P.ng_max)] : -1;
+            ok[u] = (uint32_t)b < (uint32_t)P.n;
+            bb[u] = ok[u] ? b : (int32_t)a;
+        }
+        PosM q[kBatch];
+        float mb[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            q[u] = pm[bb[u]];
+            mb[u] = mf[bb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (!ok[u]) continue;
+            float dx, dy, dz;
+            const float r2 = disp_m(g, pa, q[u], dx, dy, dz);
+            float S, vdS;
+            sinc_terms_f(r2 * tsc, P.sinc_n, S, vdS);
+            sS += (double)(mb[u] * S);
+            sD += (double)(mb[u] * (3.0f * S + vdS));
+        }
     }
     const double w0 = P.bn / (ha * ha * ha);
     const double r = w0 * sS;
@@ -203,7 +218,7 @@ __device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, double c1
     return q;
 }
 
-__global__ __launch_bounds__(kBlock) void k_iad_m(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m(Params P, Domain* __restrict__ dom,
                                                   const int32_t* __restrict__ nc,
                                                   const int32_t* __restrict__ list,
                                                   const PosM* __restrict__ pm,
@@ -226,20 +241,36 @@ __global__ __launch_bounds__(kBlock) void k_iad_m(Params P, Domain* __restrict__
     const float w0 = (float)(P.bn / (ha * ha * ha));
     const int cnt = min(nc[a], P.ng_max);
     double t11 = 0, t12 = 0, t13 = 0, t22 = 0, t23 = 0, t33 = 0;
-#pragma unroll 2
-    for (int j = 0; j < cnt; ++j) {
-        int32_t b = list[lpos(a, j, P.ng_max)];
-        if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
-        float dx, dy, dz;
-        float r2 = disp_m(g, pa, pm[b], dx, dy, dz);
-        const float s = vol[b] * (w0 * sinc_S_f(r2 * tsc, P.sinc_n));
-        const float sx = s * dx, sy = s * dy, sz = s * dz;
-        t11 += (double)(sx * dx);
-        t12 += (double)(sx * dy);
-        t13 += (double)(sx * dz);
-        t22 += (double)(sy * dy);
-        t23 += (double)(sy * dz);
-        t33 += (double)(sz * dz);
+    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+        int32_t bb[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int32_t b = (j0 + u < cnt) ? list[lpos(a, j0 + u, P.ng_max)] : -1;
+            ok[u] = (uint32_t)b < (uint32_t)P.n;
+            bb[u] = ok[u] ? b : (int32_t)a;
+        }
+        PosM q[kBatch];
+        float vb[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            q[u] = pm[bb[u]];
+            vb[u] = vol[bb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (!ok[u]) continue;
+            float dx, dy, dz;
+            const float r2 = disp_m(g, pa, q[u], dx, dy, dz);
+            const float sw = vb[u] * (w0 * sinc_S_f(r2 * tsc, P.sinc_n));
+            const float sx = sw * dx, sy = sw * dy, sz = sw * dz;
+            t11 += (double)(sx * dx);
+            t12 += (double)(sx * dy);
+            t13 += (double)(sx * dz);
+            t22 += (double)(sy * dy);
+            t23 += (double)(sy * dz);
+            t33 += (double)(sz * dz);
+        }
     }
     // 3x3 inversion in FP64
     double a11 = t22 * t33 - t23 * t23;
@@ -280,7 +311,7 @@ struct MomOutM {
 
 __global__ void k_dtmin_begin_m(Domain* d) { d->dtmin_bits = ord_bits(INFINITY); }
 
-__global__ __launch_bounds__(kBlock) void k_momentum_energy_m(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momentum_energy_m(Params P, Domain* __restrict__ dom,
                                                               const int32_t* __restrict__ nc,
                                                               const int32_t* __restrict__ ns,
                                                               const int32_t* __restrict__ list,
@@ -311,15 +342,33 @@ __global__ __launch_bounds__(kBlock) void k_momentum_energy_m(Params P, Domain* 
         const int co = min(ns[a] - nc[a], ng);
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
-#pragma unroll 2
-        for (int k = 0; k < total; ++k) {
-            const bool gather = k < cg;
-            const int j = gather ? k : ng - 1 - (k - cg);
-            const int32_t b = list[lpos(a, j, ng)];
-            if ((uint64_t)(uint32_t)b >= (uint64_t)P.n) continue;
-            const RecM rb = rec[b];
+        constexpr int kB = SPH_MOM_BATCH;
+        for (int k0 = 0; k0 < total; k0 += kB) {
+            int32_t bbv[kB];
+            bool okv[kB], gatv[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int k = k0 + u;
+                gatv[u] = k < cg;
+                const int j = gatv[u] ? k : ng - 1 - (k - cg);
+                const int32_t b = (k < total) ? list[lpos(a, j, ng)] : -1;
+                okv[u] = (uint32_t)b < (uint32_t)P.n;
+                bbv[u] = okv[u] ? b : (int32_t)a;
+            }
+            RecM rbv[kB];
+            PosM qv[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                rbv[u] = rec[bbv[u]];
+                qv[u] = pm[bbv[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+            if (!okv[u]) continue;
+            const bool gather = gatv[u];
+            const RecM& rb = rbv[u];
             float dx, dy, dz;
-            const float r2 = disp_m(g, pa, pm[b], dx, dy, dz);
+            const float r2 = disp_m(g, pa, qv[u], dx, dy, dz);
             float Wa = 0.0f;
             if (gather) Wa = w0a * sinc_S_f(r2 * tsa, P.sinc_n);
             // support of W(h_b): v_b < 2, i.e. t_b < pi^2
@@ -351,6 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_energy_m(Params P, Domain* 
             azs += (double)(-(mb * (pa_ * Aaz + rb.pb * Abz)) - gz);
             e1 += (double)(mb * (vx * Aax + vy * Aay + vz * Aaz));
             e2 += (double)(vx * gx + vy * gy + vz * gz);
+            }
         }
         // the energy rate is assembled in FP64
         const double du = (double)pa_ * e1 + 0.5 * e2;

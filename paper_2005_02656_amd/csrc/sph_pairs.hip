@@ -10,11 +10,6 @@
 // on floating-point values.
 #include "sph_common.h"
 
-// neighbours whose records the momentum/energy loop loads before computing
-#ifndef SPH_MOM_BATCH
-#define SPH_MOM_BATCH 2
-#endif
-
 namespace sph {
 namespace {
 

@@ -23,6 +23,11 @@ namespace {
 
 constexpr double kCullMargin = 1e-9;  // relative to the cell edge
 
+// particle records of one cell loaded together by the cell walk
+#ifndef SPH_CELL_BATCH
+#define SPH_CELL_BATCH 4
+#endif
+
 // spread the low 10 bits of v to every third bit (cell coordinates, level <= 9)
 __device__ __forceinline__ uint32_t spread10(uint32_t v)
 {
@@ -109,7 +114,7 @@ __device__ __forceinline__ void walk_cells(const Params& P, const Domain& D,
                                            double za, double R, Want&& want, Body&& body)
 {
     constexpr int kRow = 8;
-    constexpr int kCellBatch = 4;
+    constexpr int kCellBatch = SPH_CELL_BATCH;
     const int nax = D.ncell_axis;
     AxisWalk wx = axis_walk(P, D, 0, xa, R);
     AxisWalk wy = axis_walk(P, D, 1, ya, R);
@@ -294,14 +299,11 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 // factor of this pass), by the same per-target cell walk.  (A wavefront walking the union of its 64 targets'
 // stencils, with scalar or LDS-staged particle loads, tested 2.4x more pairs
 // and ran 1.6-2.1x slower at 64 M particles.)
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_candidates(Params P, Domain* __restrict__ dom,
-                                                       const CellRange* __restrict__ cells,
-                                                       const Pos4* __restrict__ p4,
-                                                       int32_t* __restrict__ nk,
-                                                       int32_t* __restrict__ cand,
-                                                       double kap, int only_if_refit)
+__device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__ dom,
+                                           const CellRange* __restrict__ cells,
+                                           const Pos4* __restrict__ p4, int32_t* __restrict__ nk,
+                                           int32_t* __restrict__ cand, double kap)
 {
-    if (only_if_refit && dom->refit == 0u) return;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
@@ -343,6 +345,21 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_cand
     if (k > cap) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
 }
 
+// the short-reach pass, and the full-reach pass that runs only if flagged
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_candidates(
+    Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
+    const Pos4* __restrict__ p4, int32_t* __restrict__ nk, int32_t* __restrict__ cand, double kap)
+{
+    candidates(P, dom, cells, p4, nk, cand, kap);
+}
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_candidates_full(
+    Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
+    const Pos4* __restrict__ p4, int32_t* __restrict__ nk, int32_t* __restrict__ cand, double kap)
+{
+    if (dom->refit == 0u) return;
+    candidates(P, dom, cells, p4, nk, cand, kap);
+}
+
 // one chunk of 8 candidates of slot a (entries at or past cnt read as a itself)
 __device__ __forceinline__ void load_chunk(const int32_t* __restrict__ cand, int64_t a, int j0,
                                            int cap, int cnt, int32_t bb[8])
@@ -355,14 +372,12 @@ __device__ __forceinline__ void load_chunk(const int32_t* __restrict__ cand, int
 }
 
 // Newton iterations summing over the candidate list (self term added: S(0) = 1)
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_update_h_list(Params P, Domain* __restrict__ dom,
-                                                          const int32_t* __restrict__ nk,
-                                                          const int32_t* __restrict__ cand,
-                                                          const Pos4* __restrict__ p4,
-                                                          double* __restrict__ h, double lam,
-                                                          int only_if_refit)
+__device__ __forceinline__ void update_h_list(const Params& P, Domain* __restrict__ dom,
+                                              const int32_t* __restrict__ nk,
+                                              const int32_t* __restrict__ cand,
+                                              const Pos4* __restrict__ p4, double* __restrict__ h,
+                                              double lam)
 {
-    if (only_if_refit && dom->refit == 0u) return;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
@@ -414,6 +429,22 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_upda
     } else {
         check_cell_range(P, dom, hc);
     }
+}
+
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_update_h_list(
+    Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
+    const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
+    double lam)
+{
+    update_h_list(P, dom, nk, cand, p4, h, lam);
+}
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_update_h_list_full(
+    Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
+    const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
+    double lam)
+{
+    if (dom->refit == 0u) return;
+    update_h_list(P, dom, nk, cand, p4, h, lam);
 }
 
 // exact lists from the candidates with the final h (same layout as k_find_neighbors)
@@ -519,16 +550,15 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     // short reach first; the full-reach pair runs only if an h left it (the
     // kernels read the device flag and return at once when it is clear)
     const double lam = fmin(kFusedReach, P.kappa);
-    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand, lam, 0);
+    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand, lam);
     mk.at(1, s);
     if (P.newton_iters > 0) {
-        k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h, lam,
-                                                        0);
+        k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h, lam);
         if (lam < P.kappa) {
-            k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand,
-                                                         P.kappa, 1);
-            k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h,
-                                                            P.kappa, 1);
+            k_candidates_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk,
+                                                              W.cand, P.kappa);
+            k_update_h_list_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
+                                                                 p->h, P.kappa);
         }
     }
     mk.at(2, s);
