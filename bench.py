@@ -47,10 +47,16 @@ WORKLOADS = {
 # (k_g gather pairs, k_s symmetric pairs per particle), candidate pair for the
 # Newton iterations.  Bytes are HBM bytes with every datum read or written once.
 FLOPS_PER_PAIR = {
-    "newton_h": 80,          # per candidate pair and iteration: r^2, S and v dS/dv series
-    "density": 80,           # r^2, S and v dS/dv by 16- and 15-term series, two sums
-    "iad": 63,               # r^2, S series, V W, six d_i d_j products accumulated
-    "momentum_energy": 175,  # r^2, W(h_a) and W(h_b), C_a d and C_b d, AV, a and du terms
+    # r^2 (8), t (1), sinc and x sinc' polynomials (11 + 10 terms: 39), s^n, S,
+    # v dS/dv (6), the two sums (2)
+    "newton_h": 56,
+    # as Newton, with mass-weighted sums (6)
+    "density": 60,
+    # r^2, t, sinc polynomial and s^n (33), V W (2), six d_i d_j products summed (15)
+    "iad": 50,
+    # r^2, W(h_a) and W(h_b) (55), C_a d and C_b d scaled by W (36), v_ab, x.v, AV
+    # (16), g, the pressure terms and a (30), e1 and e2 (13)
+    "momentum_energy": 160,
 }
 
 
@@ -128,8 +134,9 @@ def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload):
     kern = PHASE_KERNEL[dom]
     res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom],
            "traffic": traffic_from_profile(kern, workload)}
-    pairs = {"newton_h": None, "density": k_g * n, "iad": k_g * n, "momentum_energy": k_s * n}
-    if dom in FLOPS_PER_PAIR and pairs[dom] is not None:
+    pairs = {"newton_h": iters * k_c * n, "density": k_g * n, "iad": k_g * n,
+             "momentum_energy": k_s * n}
+    if dom in FLOPS_PER_PAIR and pairs.get(dom):
         fl = FLOPS_PER_PAIR[dom] * pairs[dom]
         alu = fl / t / 1e12
         res["alt"] = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -285,6 +292,10 @@ def main():
     step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters)
                      for k in phases) * n
     out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    step_flops = n * (FLOPS_PER_PAIR["newton_h"] * cfg.newton_iters * k_c
+                      + FLOPS_PER_PAIR["density"] * k_g + FLOPS_PER_PAIR["iad"] * k_g
+                      + FLOPS_PER_PAIR["momentum_energy"] * k_s)
+    out["step_fp64_valu_frac"] = step_flops / (ms * 1e-3) / (FP64_VALU_PEAK_TFLOPS * 1e12)
 
     if not args.no_mixed and prec == sph.FP64:
         mcfg = cfg.replace(precision=sph.MIXED)
