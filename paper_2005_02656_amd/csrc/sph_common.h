@@ -276,6 +276,20 @@ SPH_DEV double sinc_S(double t, int n)
 #ifndef SPH_WAVES_SEARCH
 #define SPH_WAVES_SEARCH 3
 #endif
+#ifndef SPH_WAVES_CAND
+#define SPH_WAVES_CAND 6
+#endif
+// the candidate walk runs best with exactly this many (registers held to fit):
+// its dependent cell-record -> particle-record round trips need resident
+// wavefronts more than batches in flight
+#ifndef SPH_WAVES_CAND_EXACT
+#define SPH_WAVES_CAND_EXACT 1
+#endif
+#if SPH_WAVES_CAND_EXACT
+#define SPH_WAVES_CAND_ATTR __attribute__((amdgpu_waves_per_eu(SPH_WAVES_CAND, SPH_WAVES_CAND)))
+#else
+#define SPH_WAVES_CAND_ATTR SPH_WAVES_CAP(SPH_WAVES_CAND)
+#endif
 #ifndef SPH_WAVES_MIXED
 #define SPH_WAVES_MIXED 2
 #endif

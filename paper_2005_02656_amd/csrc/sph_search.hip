@@ -23,9 +23,17 @@ namespace {
 
 constexpr double kCullMargin = 1e-9;  // relative to the cell edge
 
-// particle records of one cell loaded together by the cell walk
+// particle records of one cell loaded together by the cell walk, and cell
+// records of one row along x loaded together
 #ifndef SPH_CELL_BATCH
-#define SPH_CELL_BATCH 4
+#define SPH_CELL_BATCH 2
+#endif
+#ifndef SPH_CELL_ROW
+#define SPH_CELL_ROW 2
+#endif
+// 1: one 4-byte store per candidate instead of whole chunks from registers
+#ifndef SPH_CAND_DIRECT
+#define SPH_CAND_DIRECT 0
 #endif
 
 // spread the low 10 bits of v to every third bit (cell coordinates, level <= 9)
@@ -113,7 +121,7 @@ __device__ __forceinline__ void walk_cells(const Params& P, const Domain& D,
                                            const Pos4* __restrict__ p4, double xa, double ya,
                                            double za, double R, Want&& want, Body&& body)
 {
-    constexpr int kRow = 8;
+    constexpr int kRow = SPH_CELL_ROW;
     constexpr int kCellBatch = SPH_CELL_BATCH;
     const int nax = D.ncell_axis;
     AxisWalk wx = axis_walk(P, D, 0, xa, R);
@@ -334,25 +342,31 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
             double R = 2.0 * kap * fmax(ha, q.h);
             if (r2 < R * R) {
                 if (k < cap) {
+#if SPH_CAND_DIRECT
+                    cand[lpos8(a, k, cap)] = b;
+#else
                     buf[k & 7] = b;
                     if ((k & 7) == 7) flush(k & ~7);
+#endif
                 }
                 ++k;
             }
         });
+#if !SPH_CAND_DIRECT
     if (k < cap && (k & 7) != 0) flush(k & ~7);   // the partial last chunk
+#endif
     nk[a] = k;
     if (k > cap) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
 }
 
 // the short-reach pass, and the full-reach pass that runs only if flagged
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_candidates(
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, int32_t* __restrict__ nk, int32_t* __restrict__ cand, double kap)
 {
     candidates(P, dom, cells, p4, nk, cand, kap);
 }
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_candidates_full(
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates_full(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, int32_t* __restrict__ nk, int32_t* __restrict__ cand, double kap)
 {
