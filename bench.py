@@ -50,8 +50,10 @@ FLOPS_PER_PAIR = {
     # r^2 (8), t (1), sinc and x sinc' polynomials (11 + 10 terms: 39), s^n, S,
     # v dS/dv (6), the two sums (2)
     "newton_h": 56,
-    # as Newton, with mass-weighted sums (6)
+    # as Newton, with mass-weighted sums (6); in the fused step the list filter
+    # does this work for the gather pairs
     "density": 60,
+    "lists": 60,
     # r^2, t, sinc polynomial and s^n (33), V W (2), six d_i d_j products summed (15)
     "iad": 50,
     # r^2, W(h_a) and W(h_b) (55), C_a d and C_b d scaled by W (36), v_ab, x.v, AV
@@ -60,7 +62,7 @@ FLOPS_PER_PAIR = {
 }
 
 
-def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2):
+def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True):
     """Algorithmic HBM bytes per particle of one phase of sph_step."""
     return {
         # bbox (x y z h), keys, 8 radix passes over 8-byte keys and 4-byte indices,
@@ -71,9 +73,11 @@ def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2):
         "candidates": 32 + 4 + 4 * k_c,
         # p4 read, candidate list read once per iteration, h written
         "newton_h": 32 + 8 + 4 * k_c * iters,
-        # p4 repack, candidates read, counts and the filtered list written
-        "lists": 64 + 4 + 4 * k_c + 8 + 4 * k_s,
-        "density": (100 if wc else 84) + 4 * k_g,     # p4 m u (p_ref rho_ref), out 4 fields
+        # p4 repack, candidates read, counts and the filtered list written, and
+        # (fused step) the density's own fields: m u (p_ref rho_ref) in, 4 out
+        "lists": 64 + 4 + 4 * k_c + 8 + 4 * k_s + ((64 if wc else 48) if fused else 0),
+        # separate density pass (stage path): p4 m u (p_ref rho_ref), list, 4 out
+        "density": 0 if fused else (100 if wc else 84) + 4 * k_g,
         "iad": 24 + 32 + 72 + 4 + 4 * k_g + 48 + 128,  # vol, p4, rec sources, list, C, records
         "momentum_energy": 32 + 128 + 8 + 8 + 4 * k_s + 32,  # p4, record, u, counts, list, out
         "integrate": 13 * 8 + 4 * 8 + 11 * 8,          # state + rates in, state out
@@ -123,19 +127,19 @@ def traffic_from_profile(kernel, workload):
         return None
 
 
-def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload):
+def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload, fused):
     """Roofline of the phase that takes the longest.  Both ceilings are evaluated
     (algorithmic HBM bytes against 8 TB/s, algorithmic FP64 flops against the
     78.6 TFLOP/s vector peak); the binding one (larger fraction) is reported."""
     dom = max(phases, key=phases.get)
     t = phases[dom] * 1e-3
-    by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters)
+    by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters, fused)
     hbm = by * n / t / 1e9
     kern = PHASE_KERNEL[dom]
     res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom],
            "traffic": traffic_from_profile(kern, workload)}
-    pairs = {"newton_h": iters * k_c * n, "density": k_g * n, "iad": k_g * n,
-             "momentum_energy": k_s * n}
+    pairs = {"newton_h": iters * k_c * n, "density": k_g * n, "lists": k_g * n,
+             "iad": k_g * n, "momentum_energy": k_s * n}
     if dom in FLOPS_PER_PAIR and pairs.get(dom):
         fl = FLOPS_PER_PAIR[dom] * pairs[dom]
         alu = fl / t / 1e12
@@ -288,12 +292,14 @@ def main():
         nk, _ = sph.candidates_view(cfg, ws)
         k_c = float(nk.double().mean())
         out["config"]["candidates_mean"] = k_c
-    out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters, k_c, args.workload)
-    step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters)
+    out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters, k_c, args.workload,
+                               cfg.h_ratio_max <= 1.25)
+    fused = cfg.h_ratio_max <= 1.25
+    step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters, fused)
                      for k in phases) * n
     out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
     step_flops = n * (FLOPS_PER_PAIR["newton_h"] * cfg.newton_iters * k_c
-                      + FLOPS_PER_PAIR["density"] * k_g + FLOPS_PER_PAIR["iad"] * k_g
+                      + FLOPS_PER_PAIR["lists"] * k_g + FLOPS_PER_PAIR["iad"] * k_g
                       + FLOPS_PER_PAIR["momentum_energy"] * k_s)
     out["step_fp64_valu_frac"] = step_flops / (ms * 1e-3) / (FP64_VALU_PEAK_TFLOPS * 1e12)
 

@@ -339,12 +339,14 @@ sph_status step_rates(Ctx& c, sph_particles* p, sph_globals* g, const Marks& mk 
     // the cell build packs positions; with a small clamp ratio one cell walk
     // feeds both the Newton iterations and the lists (fused), else the walks of
     // the stage entry points run; the IAD pass writes the momentum records
-    if (c.P.cand_cap > 0) {
+    const bool fused = c.P.cand_cap > 0;
+    if (fused) {
         // the fused launcher re-records event 1 after its cell h_max pass, so
-        // that phase 2 holds the candidate walk alone
+        // that phase 2 holds the candidate walk alone; its list filter also
+        // forms the density (FP64 in both precisions)
         Marks sub;
         if (mk.ev && mk.n > 1) sub = Marks{mk.ev + 1, mk.n - 1};
-        if ((e = launch_fused_h_lists(c.P, c.L, c.W, p, c.s, sub))) return SPH_E_HIP;
+        if ((e = launch_fused_h_lists(c.P, c.L, c.W, p, c.s, sub, true))) return SPH_E_HIP;
     } else {
         if ((e = launch_update_h(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
         mk.at(2, c.s);
@@ -353,13 +355,15 @@ sph_status step_rates(Ctx& c, sph_particles* p, sph_globals* g, const Marks& mk 
     }
     mk.at(4, c.s);
     if (c.P.precision == SPH_MIXED) {
-        if ((e = launch_density_mixed(c.P, c.L, c.W, p, c.s, true))) return SPH_E_HIP;
+        if (fused) e = launch_pack_posm(c.P, c.W, p, c.s);
+        else e = launch_density_mixed(c.P, c.L, c.W, p, c.s, true);
+        if (e) return SPH_E_HIP;
         mk.at(5, c.s);
         if ((e = launch_iad_mixed(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
         mk.at(6, c.s);
         if ((e = launch_momentum_energy_mixed(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
     } else {
-        if ((e = launch_density(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
+        if (!fused && (e = launch_density(c.P, c.L, c.W, p, c.s, false))) return SPH_E_HIP;
         mk.at(5, c.s);
         if ((e = launch_iad(c.P, c.L, c.W, p, c.s, false, true))) return SPH_E_HIP;
         mk.at(6, c.s);

@@ -276,6 +276,17 @@ SPH_DEV double sinc_S(double t, int n)
 #ifndef SPH_WAVES_SEARCH
 #define SPH_WAVES_SEARCH 3
 #endif
+// exactly n wavefronts per SIMD (the compiler holds the registers to fit)
+#define SPH_WAVES_EXACT(n) __attribute__((amdgpu_waves_per_eu(n, n)))
+#ifndef SPH_NEWTON_ATTR
+#define SPH_NEWTON_ATTR SPH_WAVES_CAP(SPH_WAVES_SEARCH)
+#endif
+#ifndef SPH_FILTER_ATTR
+#define SPH_FILTER_ATTR SPH_WAVES_CAP(SPH_WAVES_SEARCH)
+#endif
+#ifndef SPH_MOM_ATTR
+#define SPH_MOM_ATTR SPH_WAVES_CAP(SPH_WAVES_MOM)
+#endif
 #ifndef SPH_WAVES_CAND
 #define SPH_WAVES_CAND 6
 #endif
@@ -293,6 +304,35 @@ SPH_DEV double sinc_S(double t, int n)
 #ifndef SPH_WAVES_MIXED
 #define SPH_WAVES_MIXED 2
 #endif
+
+// Density, grad-h term and EOS of slot a from its two density sums
+// sS = sum m_b S, sD = sum m_b (3 S + v dS/dv) over N(a) and a itself (eq. 1;
+// Omega = 1 + h/(3 rho) sum m dW/dh with dW/dh = -(B/h^4)(3 S + v dS/dv)).
+struct DensOut {
+    const double *m, *u, *p_ref, *rho_ref;
+    double *rho, *omega, *p, *c;
+};
+SPH_DEV void finish_density(const Params& P, Domain* dom, const DensOut& O, int64_t a, double ha,
+                            double sS, double sD)
+{
+    const double w0 = P.bn / (ha * ha * ha);
+    const double r = w0 * sS;
+    const double om = 1.0 - w0 * sD / (3.0 * r);
+    double pr, c;
+    if (P.eos == SPH_EOS_IDEAL) {
+        pr = (P.gamma - 1.0) * r * O.u[a];
+        c = sqrt(P.gamma * (P.gamma - 1.0) * O.u[a]);
+    } else {
+        pr = O.p_ref[a] + P.c0 * P.c0 * (r - O.rho_ref[a]);
+        c = P.c0;
+    }
+    O.rho[a] = r;
+    O.omega[a] = om;
+    O.p[a] = pr;
+    O.c[a] = c;
+    if (!isfinite(r) || !isfinite(om) || !isfinite(pr) || !isfinite(c))
+        set_err(dom, SPH_ERRBIT_NONFINITE);
+}
 
 // neighbours whose records the momentum/energy loops load before computing
 #ifndef SPH_MOM_BATCH
@@ -359,8 +399,12 @@ struct Marks {
         if (ev && k < n) (void)hipEventRecord(ev[k], s);
     }
 };
+// with_density: the list filter also forms rho, Omega, P and c (the gather test
+// it makes is the density's support test, with the final h)
 hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                                hipStream_t s, const Marks& mk = Marks());
+                                hipStream_t s, const Marks& mk = Marks(),
+                                bool with_density = false);
+hipError_t launch_pack_posm(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s);
 hipError_t launch_timestep(const Params& P, const Ws& W, sph_globals* g, hipStream_t s);
 hipError_t launch_integrate(const Params& P, const Ws& W, sph_particles* p, sph_globals* g,
                             hipStream_t s);

@@ -439,6 +439,13 @@ static_assert(sizeof(RecM) == 64, "RecM layout");
 size_t mixed_posm_bytes() { return sizeof(PosM); }
 size_t mixed_rec_bytes() { return sizeof(RecM); }
 
+hipError_t launch_pack_posm(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, (PosM*)W.posm, W.mf);
+    return hipGetLastError();
+}
+
 hipError_t launch_density_mixed(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
                                 hipStream_t s, bool pack)
 {

@@ -64,24 +64,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_densit
             sD += mb[u] * (3.0 * S + vdS);
         }
     }
-    const double w0 = P.bn / (ha * ha * ha);
-    const double r = w0 * sS;
-    // Omega = 1 + h/(3 rho) sum m dW/dh, dW/dh = -(B/h^4)(3S + v dS/dv)
-    const double om = 1.0 - w0 * sD / (3.0 * r);
-    double p, c;
-    if (P.eos == SPH_EOS_IDEAL) {
-        p = (P.gamma - 1.0) * r * u[a];
-        c = sqrt(P.gamma * (P.gamma - 1.0) * u[a]);
-    } else {
-        p = p_ref[a] + P.c0 * P.c0 * (r - rho_ref[a]);
-        c = P.c0;
-    }
-    rho[a] = r;
-    omega[a] = om;
-    pr[a] = p;
-    cs[a] = c;
-    if (!isfinite(r) || !isfinite(om) || !isfinite(p) || !isfinite(c))
-        set_err(dom, SPH_ERRBIT_NONFINITE);
+    finish_density(P, dom, DensOut{m, u, p_ref, rho_ref, rho, omega, pr, cs}, a, ha, sS, sD);
 }
 
 // volume m/rho of every particle (one division per particle instead of per pair)
@@ -202,7 +185,7 @@ struct MomOut {
 
 __global__ void k_dtmin_begin(Domain* d) { d->dtmin_bits = ord_bits(INFINITY); }
 
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MOM) void k_momentum_energy(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
                                                             const int32_t* __restrict__ list,

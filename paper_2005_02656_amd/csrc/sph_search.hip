@@ -445,14 +445,14 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
     }
 }
 
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_update_h_list(
+__global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
     double lam)
 {
     update_h_list(P, dom, nk, cand, p4, h, lam);
 }
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_update_h_list_full(
+__global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list_full(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
     double lam)
@@ -462,13 +462,16 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_upda
 }
 
 // exact lists from the candidates with the final h (same layout as k_find_neighbors)
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_filter(Params P, Domain* __restrict__ dom,
+// kDens: also the density sums over the gather members (the same order as the
+// density pass over the gather list), then rho, Omega and the EOS
+template <bool kDens>
+__global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Domain* __restrict__ dom,
                                                    const int32_t* __restrict__ nk,
                                                    const int32_t* __restrict__ cand,
                                                    const Pos4* __restrict__ p4,
                                                    int32_t* __restrict__ nc,
                                                    int32_t* __restrict__ ns,
-                                                   int32_t* __restrict__ list)
+                                                   int32_t* __restrict__ list, DensOut O)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
@@ -482,13 +485,23 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_filt
     const int cap = P.cand_cap;
     const int cnt = min(nk[a], cap);
     const int ng = P.ng_max;
+    const double tsc = kPiHalfSq / (ha * ha);
+    double sS = 0.0, sD = 0.0;
+    if (kDens) {
+        sS = O.m[a];          // self term: S = 1, v dS/dv = 0
+        sD = 3.0 * O.m[a];
+    }
     int cg = 0, co = 0;
     for (int j0 = 0; j0 < cnt; j0 += 8) {
         int32_t bb[8];
         load_chunk(cand, a, j0, cap, cnt, bb);
         Pos4 q[8];
+        double mb[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) q[u] = p4[bb[u]];
+        for (int u = 0; u < 8; ++u) {
+            q[u] = p4[bb[u]];
+            if (kDens) mb[u] = O.m[bb[u]];
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (j0 + u >= cnt) continue;
@@ -496,7 +509,15 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_filt
             double dx, dy, dz;
             double r2 = disp(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
             if (r2 < Ra2) {
-                if (cg < ng) list[lpos(a, cg, ng)] = b;
+                if (cg < ng) {
+                    list[lpos(a, cg, ng)] = b;
+                    if (kDens) {
+                        double S, vdS;
+                        sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
+                        sS += mb[u] * S;
+                        sD += mb[u] * (3.0 * S + vdS);
+                    }
+                }
                 ++cg;
             } else {
                 double hb2 = 2.0 * fmax(ha, q[u].h);
@@ -510,6 +531,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_SEARCH) void k_filt
     nc[a] = cg;
     ns[a] = cg + co;
     if (cg + co > ng) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
+    if (kDens) finish_density(P, dom, O, a, ha, sS, sD);
 }
 
 }  // namespace
@@ -554,7 +576,7 @@ hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
 // fused: candidates at h0, Newton over candidates, exact lists at the new h.
 // Expects the packed positions of the cell build (h0 in them).
 hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
-                                hipStream_t s, const Marks& mk)
+                                hipStream_t s, const Marks& mk, bool with_density)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
@@ -578,7 +600,13 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     mk.at(2, s);
     hipError_t e = launch_pack_p4(P, W, p, s);
     if (e != hipSuccess) return e;
-    k_filter<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns, W.list);
+    const DensOut O{p->m, p->u, p->p_ref, p->rho_ref, p->rho, p->omega, p->p, p->c};
+    if (with_density)
+        k_filter<true><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns,
+                                                       W.list, O);
+    else
+        k_filter<false><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns,
+                                                        W.list, O);
     return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ def source_digest() -> str:
 
 
 def short(name: str) -> str:
-    m = re.search(r"(k_\w+)\(", name)
+    m = re.search(r"(k_\w+)(?:<[^>]*>)?\(", name)
     if m:
         return m.group(1)
     m = re.search(r"(__amd_rocclr_\w+)", name)
