@@ -214,9 +214,11 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
         constexpr int kMomBatch = SPH_MOM_BATCH;
-        for (int k0 = 0; k0 < total; k0 += kMomBatch) {
+        // list entries and records of the batch starting at k0 (entries past
+        // the end read the target itself and are skipped)
+        auto load = [&](int k0, bool (&ok)[kMomBatch], bool (&gat)[kMomBatch],
+                        Pos4 (&qb)[kMomBatch], MomRec (&rbb)[kMomBatch]) {
             int32_t bb[kMomBatch];
-            bool ok[kMomBatch], gat[kMomBatch];
 #pragma unroll
             for (int u = 0; u < kMomBatch; ++u) {
                 const int k = k0 + u;
@@ -226,19 +228,13 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
                 ok[u] = (uint32_t)b < (uint32_t)P.n;
                 bb[u] = ok[u] ? b : (int32_t)a;
             }
-            Pos4 qb[kMomBatch];
-            MomRec rbb[kMomBatch];
 #pragma unroll
             for (int u = 0; u < kMomBatch; ++u) {
                 qb[u] = p4[bb[u]];
                 rbb[u] = rec[bb[u]];
             }
-#pragma unroll
-            for (int u = 0; u < kMomBatch; ++u) {
-            if (!ok[u]) continue;
-            const bool gather = gat[u];
-            const Pos4& q = qb[u];
-            const MomRec& rb = rbb[u];
+        };
+        auto pair = [&](bool gather, const Pos4& q, const MomRec& rb) {
             double dx, dy, dz;
             double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
             double Wa = 0.0;
@@ -275,7 +271,19 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             azs += -(mb * (pa_ * Aaz + rb.pb * Abz)) - gz;
             e1 += mb * (vx * Aax + vy * Aay + vz * Aaz);
             e2 += vx * gx + vy * gy + vz * gz;
-            }
+        };
+        auto compute = [&](const bool (&ok)[kMomBatch], const bool (&gat)[kMomBatch],
+                           const Pos4 (&qb)[kMomBatch], const MomRec (&rbb)[kMomBatch]) {
+#pragma unroll
+            for (int u = 0; u < kMomBatch; ++u)
+                if (ok[u]) pair(gat[u], qb[u], rbb[u]);
+        };
+        bool okA[kMomBatch], gatA[kMomBatch];
+        Pos4 qA[kMomBatch];
+        MomRec rA[kMomBatch];
+        for (int k0 = 0; k0 < total; k0 += kMomBatch) {
+            load(k0, okA, gatA, qA, rA);
+            compute(okA, gatA, qA, rA);
         }
         const double du = pa_ * e1 + 0.5 * e2;
         O.ax[a] = axs;

@@ -129,7 +129,9 @@ def gaussian_blob(n: int, seed: int = 3, seed_v: int = 33, amp: float = 10.0,
                vx=v[0].copy(), vy=v[1].copy(), vz=v[2].copy(),
                m=np.full(n, 1.0 / n), u=np.ones(n),
                h=H_GUESS_SPACINGS * n_local ** (-1.0 / 3.0), id=np.arange(n, dtype=np.int64))
-    return Workload(f"gaussian_blob{n}", arr, base_params())
+    # Poisson clumps hold up to ~260 neighbours within 2h once h has converged
+    # (8M particles), so a larger list capacity than the lattices' 160
+    return Workload(f"gaussian_blob{n}", arr, base_params(ng_max=320))
 
 
 def random_periodic(n: int, seed: int, h_lo: float, h_hi: float, sigma_v: float = 0.3,

@@ -1,8 +1,7 @@
 """Parity at the workloads' full sizes (1 M, 8 M and 64 M particles), in the
 launch configuration the benchmark times (sph_step, the workload's own config):
 one step from the generator's state, then sampled targets checked against the
-oracle (the blob with a list capacity of 256 instead of 160, since it starts
-from the generator's rough h).
+oracle.
 
 The oracle computes every sampled value from the generator's inputs alone.  It
 runs on a spatial subset that holds every particle the targets' values depend
@@ -32,7 +31,7 @@ FULL = {
     "c2": (inputs.c2_square_patch, [(0.0, 0.0, 0.0), (0.495, -0.495, 0.1), (0.2, -0.3, 0.4995)],
            None),
     "c3": (inputs.c3_gaussian_blob, [(0.5, 0.5, 0.5), (0.001, 0.999, 0.3), (0.27, 0.62, 0.81)],
-           256),
+           None),
     "c4": (inputs.c4_square_patch, [(0.0, 0.0, 0.0), (-0.4995, 0.3, -0.2), (0.1, 0.1, -0.4999)],
            None),
 }
@@ -65,8 +64,6 @@ def test_fullsize_sampled(name):
         a["rho_ref"] = np.ones(n)
     cfg = sph.Config.from_params(n, w.params)           # the benchmark's configuration
     if ng is not None:
-        # the blob starts from the generator's h, not the set-up's converged one:
-        # Poisson clumps then hold more than 160 neighbours, so a larger capacity
         cfg = cfg.replace(ng_max=ng)
     _, ocfg = configs(w)
     parts = sph.Particles.from_arrays(a, cfg)
