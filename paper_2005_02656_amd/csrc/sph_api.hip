@@ -38,6 +38,7 @@ Layout make_layout(int64_t n, int ng_max)
     L.p4 = take(sizeof(Pos4) * n);
     L.rec = take(sizeof(MomRec) * n);
     L.vol = take(sizeof(double) * n);
+    L.pv = take(sizeof(PosV) * n);
     const size_t padded = (size_t)((n + 63) / 64) * 64;   // lists are tiled by 64 slots
     size_t lst = sizeof(int32_t) * (size_t)ng_max * padded;
     size_t tmp = sizeof(double) * kMaxPermFields * n;
@@ -75,6 +76,7 @@ Ws carve(void* ws, const Layout& L)
     W.p4 = (Pos4*)(b + L.p4);
     W.rec = (MomRec*)(b + L.rec);
     W.vol = (double*)(b + L.vol);
+    W.pv = (PosV*)(b + L.pv);
     W.list = (int32_t*)(b + L.list);
     W.tmp = (double*)(b + L.list);
     return W;

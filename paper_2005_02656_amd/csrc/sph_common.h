@@ -68,11 +68,17 @@ struct Domain {
 struct alignas(32) Pos4 {
     double x, y, z, h;
 };
-// what the momentum/energy pass needs of a neighbour besides its position
+// what the IAD pass needs of a neighbour: position and volume m/rho
+struct alignas(32) PosV {
+    double x, y, z, v;
+};
+// everything the momentum/energy pass needs of a neighbour (144 B: nine
+// 16-byte loads; the gathers of this pass cost in proportion to their bytes)
 struct alignas(16) MomRec {
+    double x, y, z, h;                     // position and smoothing length
     double c11, c12, c13, c22, c23, c33;   // IAD matrix C = tau^-1
     double irho, c, pb, m;                 // 1/rho, sound speed, P/(Omega rho^2), mass
-    double vx, vy, vz, invh, pad0, pad1;
+    double vx, vy, vz, invh;
 };
 struct alignas(16) CellRange {
     int32_t s, e;   // particle slots [s, e) of one Morton cell
@@ -118,7 +124,7 @@ int candidate_capacity(int ng_max);
 // ---------------------------------------------------------------- workspace layout
 struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
-    size_t cells, nc, ns, nk, p4, rec, vol, list, cand, posm, mf, mf2;
+    size_t cells, nc, ns, nk, p4, rec, vol, pv, list, cand, posm, mf, mf2;
     size_t total;
     int64_t n, nsort_blocks, hist_len, scan_blocks, ncells_cap;
     int lcap, cand_cap;
@@ -139,6 +145,7 @@ struct Ws {
     Pos4* p4;
     MomRec* rec;
     double* vol;               // m/rho per particle (IAD pass)
+    PosV* pv;                  // position and m/rho (IAD neighbour records)
     void* posm;                // mixed precision: cell index + FP32 offsets (16 B)
     void* recm;                // mixed precision: FP32 momentum records (aliases rec)
     float *mf, *mf2;           // mixed precision: FP32 mass and volume

@@ -70,20 +70,27 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_densit
 // volume m/rho of every particle (one division per particle instead of per pair)
 __global__ __launch_bounds__(kBlock) void k_volume(int64_t n, const double* __restrict__ m,
                                                    const double* __restrict__ rho,
-                                                   double* __restrict__ vol)
+                                                   const Pos4* __restrict__ p4,
+                                                   double* __restrict__ vol,
+                                                   PosV* __restrict__ pv)
 {
     int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (i < n) vol[i] = m[i] / rho[i];
+    if (i >= n) return;
+    const double v = m[i] / rho[i];
+    const Pos4 q = p4[i];
+    vol[i] = v;
+    pv[i] = PosV{q.x, q.y, q.z, v};
 }
 
 struct RecSrc {
-    const double *m, *rho, *omega, *p, *c, *vx, *vy, *vz, *h;
+    const double *m, *rho, *omega, *p, *c, *vx, *vy, *vz, *h, *x, *y, *z;
 };
 
 __device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, double c11, double c12,
                                            double c13, double c22, double c23, double c33)
 {
     MomRec q;
+    q.x = R.x[a]; q.y = R.y[a]; q.z = R.z[a]; q.h = R.h[a];
     q.c11 = c11; q.c12 = c12; q.c13 = c13; q.c22 = c22; q.c23 = c23; q.c33 = c33;
     const double r = R.rho[a];
     q.irho = 1.0 / r;
@@ -92,7 +99,6 @@ __device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, double c1
     q.m = R.m[a];
     q.vx = R.vx[a]; q.vy = R.vy[a]; q.vz = R.vz[a];
     q.invh = 1.0 / R.h[a];
-    q.pad0 = 0.0; q.pad1 = 0.0;
     return q;
 }
 
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_iad(Pa
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ list,
                                                 const Pos4* __restrict__ p4,
-                                                const double* __restrict__ vol,
+                                                const PosV* __restrict__ pv,
                                                 double* __restrict__ c11, double* __restrict__ c12,
                                                 double* __restrict__ c13, double* __restrict__ c22,
                                                 double* __restrict__ c23, double* __restrict__ c33,
@@ -126,19 +132,15 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_iad(Pa
             ok[u] = (uint32_t)b < (uint32_t)P.n;
             bb[u] = ok[u] ? b : (int32_t)a;
         }
-        double qx[kBatch], qy[kBatch], qz[kBatch], vb[kBatch];
+        PosV q[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const Pos4* q = p4 + bb[u];
-            qx[u] = q->x; qy[u] = q->y; qz[u] = q->z;
-            vb[u] = vol[bb[u]];
-        }
+        for (int u = 0; u < kBatch; ++u) q[u] = pv[bb[u]];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             if (!ok[u]) continue;
             double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
-            double s = vb[u] * (w0 * sinc_S(r2 * tsc, P.sinc_n));
+            double r2 = disp(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
+            double s = q[u].v * (w0 * sinc_S(r2 * tsc, P.sinc_n));
             t11 += s * dx * dx;
             t12 += s * dx * dy;
             t13 += s * dx * dz;
@@ -200,9 +202,8 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
     const int64_t a = lb * kBlock + threadIdx.x;
     double dtc = INFINITY;
     if (a < P.n) {
-        const Pos4 pa = p4[a];
         const MomRec ra = rec[a];
-        const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
+        const double xa = ra.x, ya = ra.y, za = ra.z, ha = ra.h;
         const double vxa = ra.vx, vya = ra.vy, vza = ra.vz;
         const double ca = ra.c, ira = ra.irho, pa_ = ra.pb;
         const double tsa = kPiHalfSq / (ha * ha);
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
         // list entries and records of the batch starting at k0 (entries past
         // the end read the target itself and are skipped)
         auto load = [&](int k0, bool (&ok)[kMomBatch], bool (&gat)[kMomBatch],
-                        Pos4 (&qb)[kMomBatch], MomRec (&rbb)[kMomBatch]) {
+                        MomRec (&rbb)[kMomBatch]) {
             int32_t bb[kMomBatch];
 #pragma unroll
             for (int u = 0; u < kMomBatch; ++u) {
@@ -229,18 +230,15 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
                 bb[u] = ok[u] ? b : (int32_t)a;
             }
 #pragma unroll
-            for (int u = 0; u < kMomBatch; ++u) {
-                qb[u] = p4[bb[u]];
-                rbb[u] = rec[bb[u]];
-            }
+            for (int u = 0; u < kMomBatch; ++u) rbb[u] = rec[bb[u]];
         };
-        auto pair = [&](bool gather, const Pos4& q, const MomRec& rb) {
+        auto pair = [&](bool gather, const MomRec& rb) {
             double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
+            double r2 = disp(P, xa, ya, za, rb.x, rb.y, rb.z, dx, dy, dz);
             double Wa = 0.0;
             if (gather) Wa = w0a * sinc_S(r2 * tsa, P.sinc_n);
             double Wb = 0.0;
-            const double hb2 = 2.0 * q.h;
+            const double hb2 = 2.0 * rb.h;
             if (r2 < hb2 * hb2) {
                 const double ih = rb.invh, ih2 = ih * ih;
                 Wb = P.bn * (ih2 * ih) * sinc_S(r2 * (kPiHalfSq * ih2), P.sinc_n);
@@ -272,18 +270,13 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             e1 += mb * (vx * Aax + vy * Aay + vz * Aaz);
             e2 += vx * gx + vy * gy + vz * gz;
         };
-        auto compute = [&](const bool (&ok)[kMomBatch], const bool (&gat)[kMomBatch],
-                           const Pos4 (&qb)[kMomBatch], const MomRec (&rbb)[kMomBatch]) {
-#pragma unroll
-            for (int u = 0; u < kMomBatch; ++u)
-                if (ok[u]) pair(gat[u], qb[u], rbb[u]);
-        };
         bool okA[kMomBatch], gatA[kMomBatch];
-        Pos4 qA[kMomBatch];
         MomRec rA[kMomBatch];
         for (int k0 = 0; k0 < total; k0 += kMomBatch) {
-            load(k0, okA, gatA, qA, rA);
-            compute(okA, gatA, qA, rA);
+            load(k0, okA, gatA, rA);
+#pragma unroll
+            for (int u = 0; u < kMomBatch; ++u)
+                if (okA[u]) pair(gatA[u], rA[u]);
         }
         const double du = pa_ * e1 + 0.5 * e2;
         O.ax[a] = axs;
@@ -323,7 +316,8 @@ __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals
 
 RecSrc rec_src(const sph_particles* p)
 {
-    return RecSrc{p->m, p->rho, p->omega, p->p, p->c, p->vx, p->vy, p->vz, p->h};
+    return RecSrc{p->m, p->rho, p->omega, p->p, p->c, p->vx, p->vy, p->vz, p->h,
+                  p->x, p->y, p->z};
 }
 
 }  // namespace
@@ -349,8 +343,8 @@ hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particl
         if (e != hipSuccess) return e;
     }
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.vol);
-    k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, W.vol, p->c11, p->c12,
+    k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.p4, W.vol, W.pv);
+    k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12,
                                           p->c13, p->c22, p->c23, p->c33, rec_src(p),
                                           write_rec ? W.rec : nullptr);
     return hipGetLastError();
