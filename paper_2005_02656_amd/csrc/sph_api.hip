@@ -36,6 +36,7 @@ Layout make_layout(int64_t n, int ng_max)
     L.ns = take(sizeof(int32_t) * n);
     L.nk = take(sizeof(int32_t) * n);
     L.p4 = take(sizeof(Pos4) * n);
+    L.pf = take(sizeof(Pos4f) * n);
     L.rec = take(sizeof(MomRec) * n);
     L.vol = take(sizeof(double) * n);
     L.pv = take(sizeof(PosV) * n);
@@ -74,6 +75,7 @@ Ws carve(void* ws, const Layout& L)
     W.mf = (float*)(b + L.mf);
     W.mf2 = (float*)(b + L.mf2);
     W.p4 = (Pos4*)(b + L.p4);
+    W.pf = (Pos4f*)(b + L.pf);
     W.rec = (MomRec*)(b + L.rec);
     W.vol = (double*)(b + L.vol);
     W.pv = (PosV*)(b + L.pv);
@@ -129,6 +131,8 @@ Params make_params(const sph_config* cfg, double bn, int lcap, int cand_cap)
         P.box_hi[k] = cfg->box_hi[k];
         P.L[k] = cfg->box_hi[k] - cfg->box_lo[k];
         P.halfL[k] = 0.5 * P.L[k];
+        P.Lf[k] = (float)P.L[k];
+        P.halfLf[k] = (float)P.halfL[k];
         P.periodic[k] = cfg->periodic[k] ? 1 : 0;
     }
     P.sinc_n = (int)cfg->sinc_n;

@@ -99,7 +99,7 @@ __global__ void k_domain_end(Params P, Domain* d)
 {
     double hm = ord_value(d->ord_hmax);
     if (!(hm > 0.0)) hm = 0.0;
-    double D[3];
+    double D[3], ext = 0.0;
     for (int k = 0; k < 3; ++k) {
         double lo = P.periodic[k] ? P.box_lo[k] : ord_value(d->ord_min[k]);
         double hi = P.periodic[k] ? P.box_hi[k] : ord_value(d->ord_max[k]);
@@ -107,7 +107,9 @@ __global__ void k_domain_end(Params P, Domain* d)
         d->hi[k] = hi;
         D[k] = hi - lo;
         d->scale[k] = (D[k] > 0.0) ? 2097152.0 / D[k] : 0.0;
+        ext = fmax(ext, D[k]);
     }
+    d->walk_slack = (float)(ext * 0x1p-20);
     int level = 0;
     for (int l = P.lcap; l >= 0; --l) {
         bool ok = true;
@@ -364,10 +366,21 @@ __global__ __launch_bounds__(kBlock) void k_gather(PermSet S, const uint32_t* __
     for (int f = 0; f < S.nf; ++f) tmp[(int64_t)f * n + i] = S.f[f][src];
 }
 
-// copy back, and pack positions and h (fields 0, 1, 2 and 9 of the set)
+// smallest float >= v, for v > 0
+__device__ __forceinline__ float float_up(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+    return f;
+}
+
+// copy back, and pack positions and h (fields 0, 1, 2 and 9 of the set); with
+// pf, also the FP32 walk records of the fused candidate pass
 __global__ __launch_bounds__(kBlock) void k_scatter_back(PermSet S,
                                                          const uint64_t* __restrict__ tmp,
-                                                         int64_t n, Pos4* __restrict__ p4)
+                                                         int64_t n, const Domain* __restrict__ dom,
+                                                         Pos4* __restrict__ p4,
+                                                         Pos4f* __restrict__ pf)
 {
     int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
@@ -378,6 +391,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_back(PermSet S,
     q.z = __builtin_bit_cast(double, tmp[2 * n + i]);
     q.h = __builtin_bit_cast(double, tmp[9 * n + i]);
     p4[i] = q;
+    if (pf)
+        pf[i] = Pos4f{(float)(q.x - dom->lo[0]), (float)(q.y - dom->lo[1]),
+                      (float)(q.z - dom->lo[2]), float_up(q.h)};
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_p4(const double* __restrict__ x,
@@ -441,7 +457,8 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
     for (uint64_t* f : fields)
         if (f) S.f[S.nf++] = f;
     k_gather<<<grid_xcd(nb), kBlock, 0, s>>>(S, W.idx0, (uint64_t*)W.tmp, n);
-    k_scatter_back<<<nb, kBlock, 0, s>>>(S, (const uint64_t*)W.tmp, n, W.p4);
+    k_scatter_back<<<nb, kBlock, 0, s>>>(S, (const uint64_t*)W.tmp, n, W.dom, W.p4,
+                                         P.cand_cap > 0 ? W.pf : nullptr);
     return hipGetLastError();
 }
 

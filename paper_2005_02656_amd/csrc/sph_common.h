@@ -41,6 +41,7 @@ struct Params {
     int lcap;              // largest admissible cell level (8^lcap <= table size)
     int precision;
     int cand_cap;          // candidate-list capacity of the fused step (0: off)
+    float Lf[3], halfLf[3];  // L and L/2 in FP32 (the fused step's candidate walk)
 };
 
 // ---------------------------------------------------------------- device domain
@@ -59,6 +60,7 @@ struct Domain {
     int32_t level, shift, ncell_axis;
     uint32_t err;              // sticky SPH_ERRBIT_* word
     uint32_t refit;            // fused step: an h left the short candidate reach
+    float walk_slack;          // 2^-20 x the largest extent (FP32 candidate walk)
     int64_t built_n;
 };
 
@@ -67,6 +69,12 @@ struct Domain {
 // load per structure-of-arrays field.
 struct alignas(32) Pos4 {
     double x, y, z, h;
+};
+// the candidate walk's record (fused step): FP32 offsets of the position from
+// the key domain's low corner and h rounded up; the walk widens its test to
+// cover their rounding, so its candidates are a superset of the exact ones
+struct alignas(16) Pos4f {
+    float x, y, z, h;
 };
 // what the IAD pass needs of a neighbour: position and volume m/rho
 struct alignas(32) PosV {
@@ -124,7 +132,7 @@ int candidate_capacity(int ng_max);
 // ---------------------------------------------------------------- workspace layout
 struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
-    size_t cells, nc, ns, nk, p4, rec, vol, pv, list, cand, posm, mf, mf2;
+    size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm, mf, mf2;
     size_t total;
     int64_t n, nsort_blocks, hist_len, scan_blocks, ncells_cap;
     int lcap, cand_cap;
@@ -146,6 +154,7 @@ struct Ws {
     MomRec* rec;
     double* vol;               // m/rho per particle (IAD pass)
     PosV* pv;                  // position and m/rho (IAD neighbour records)
+    Pos4f* pf;                 // FP32 walk records of the fused candidate pass
     void* posm;                // mixed precision: cell index + FP32 offsets (16 B)
     void* recm;                // mixed precision: FP32 momentum records (aliases rec)
     float *mf, *mf2;           // mixed precision: FP32 mass and volume

@@ -16,6 +16,8 @@
 //    h <= kappa h0), the Newton iterations sum over the candidate list, and a
 //    filter pass writes the exact lists from the candidates with the final h.
 //    The neighbour sets are identical; only the visiting order differs.
+#include <cmath>
+
 #include "sph_common.h"
 
 namespace sph {
@@ -115,10 +117,10 @@ __device__ __forceinline__ uint32_t axis_cell(const AxisWalk& a, int o, int nax)
 // The cell records of one row (up to kRow cells along x) are loaded together,
 // then each cell's particle records in batches of four: independent loads in
 // flight instead of one dependent load per candidate.
-template <class Want, class Body>
+template <class Rec, class Want, class Body>
 __device__ __forceinline__ void walk_cells(const Params& P, const Domain& D,
                                            const CellRange* __restrict__ cells,
-                                           const Pos4* __restrict__ p4, double xa, double ya,
+                                           const Rec* __restrict__ recs, double xa, double ya,
                                            double za, double R, Want&& want, Body&& body)
 {
     constexpr int kRow = SPH_CELL_ROW;
@@ -158,9 +160,9 @@ __device__ __forceinline__ void walk_cells(const Params& P, const Domain& D,
                     if (!in[i] || !want(cr[i], g2[i])) continue;
                     const int32_t e = cr[i].e;
                     for (int32_t b0 = cr[i].s; b0 < e; b0 += kCellBatch) {
-                        Pos4 q[kCellBatch];
+                        Rec q[kCellBatch];
 #pragma unroll
-                        for (int u = 0; u < kCellBatch; ++u) q[u] = p4[min(b0 + u, e - 1)];
+                        for (int u = 0; u < kCellBatch; ++u) q[u] = recs[min(b0 + u, e - 1)];
 #pragma unroll
                         for (int u = 0; u < kCellBatch; ++u)
                             if (b0 + u < e) body(b0 + u, q[u]);
@@ -303,14 +305,25 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 }
 
 // ---------------------------------------------------------------- fused step
-// Candidates: b != a with r^2 < (2 kap max(h0_a, h0_b))^2 (kap: the reach
-// factor of this pass), by the same per-target cell walk.  (A wavefront walking the union of its 64 targets'
-// stencils, with scalar or LDS-staged particle loads, tested 2.4x more pairs
-// and ran 1.6-2.1x slower at 64 M particles.)
+// Candidates: every b != a with r^2 < (2 kap max(h0_a, h0_b))^2 (kap: the reach
+// factor of this pass), by the same per-target cell walk over 16-byte FP32
+// records.  The test runs in FP32 on offsets from the domain's low corner, with
+// the reach widened by a bound on their rounding: each offset is within
+// 2^-24 ext of its FP64 value (ext: the largest extent of the key domain) and
+// each difference or periodic shift rounds by at most as much again, so every
+// displacement component is within 5 * 2^-24 ext and the distance within
+// sqrt(3) times that, below the slack 2^-20 ext added to the reach; the factor
+// 1 + 2^-18 on the squared reach covers the FP32 rounding of r^2 and of the
+// reach itself.  The extras are at most a relative 1e-4 beyond the reach at
+// the benchmark sizes, and the passes after this one test every candidate in
+// FP64.  (A wavefront walking the union of its 64 targets' stencils, with
+// scalar or LDS-staged particle loads, tested 2.4x more pairs and ran 1.6-2.1x
+// slower at 64 M particles.)
 __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__ dom,
                                            const CellRange* __restrict__ cells,
-                                           const Pos4* __restrict__ p4, int32_t* __restrict__ nk,
-                                           int32_t* __restrict__ cand, double kap)
+                                           const Pos4* __restrict__ p4,
+                                           const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
+                                           int32_t* __restrict__ cand, double kap, float k2f)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
@@ -319,9 +332,10 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
     if (a >= P.n) return;
     const Domain D = *dom;
     const Pos4 pa = p4[a];
-    const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
+    const Pos4f fa = pf[a];
     const double hmax0 = ord_value(D.hmax_new_bits);
     const int cap = P.cand_cap;
+    const float slack = D.walk_slack;
     int k = 0;
     int32_t buf[8];
     auto flush = [&](int j0) {
@@ -330,17 +344,23 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
         dst[1] = make_int4(buf[4], buf[5], buf[6], buf[7]);
     };
     walk_cells(
-        P, D, cells, p4, xa, ya, za, 2.0 * kap * fmax(ha, hmax0),
+        P, D, cells, pf, pa.x, pa.y, pa.z, 2.0 * kap * fmax((double)fa.h, hmax0),
         [&](const CellRange& cr, double g2) {
-            double hc = 2.0 * kap * fmax(ha, cr.hmax);
+            double hc = 2.0 * kap * fmax((double)fa.h, cr.hmax);
             return g2 < hc * hc;
         },
-        [&](int32_t b, const Pos4& q) {
+        [&](int32_t b, const Pos4f& q) {
             if (b == a) return;
-            double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
-            double R = 2.0 * kap * fmax(ha, q.h);
-            if (r2 < R * R) {
+            float d[3] = {q.x - fa.x, q.y - fa.y, q.z - fa.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (P.periodic[c]) {
+                    if (d[c] > P.halfLf[c]) d[c] -= P.Lf[c];
+                    else if (d[c] <= -P.halfLf[c]) d[c] += P.Lf[c];
+                }
+            const float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const float R = k2f * fmaxf(fa.h, q.h) + slack;
+            if (r2 < (R * R) * (1.0f + 0x1p-18f)) {
                 if (k < cap) {
 #if SPH_CAND_DIRECT
                     cand[lpos8(a, k, cap)] = b;
@@ -362,16 +382,18 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
 // the short-reach pass, and the full-reach pass that runs only if flagged
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
-    const Pos4* __restrict__ p4, int32_t* __restrict__ nk, int32_t* __restrict__ cand, double kap)
+    const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
+    int32_t* __restrict__ cand, double kap, float k2f)
 {
-    candidates(P, dom, cells, p4, nk, cand, kap);
+    candidates(P, dom, cells, p4, pf, nk, cand, kap, k2f);
 }
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates_full(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
-    const Pos4* __restrict__ p4, int32_t* __restrict__ nk, int32_t* __restrict__ cand, double kap)
+    const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
+    int32_t* __restrict__ cand, double kap, float k2f)
 {
     if (dom->refit == 0u) return;
-    candidates(P, dom, cells, p4, nk, cand, kap);
+    candidates(P, dom, cells, p4, pf, nk, cand, kap, k2f);
 }
 
 // one chunk of 8 candidates of slot a (entries at or past cnt read as a itself)
@@ -573,8 +595,15 @@ hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
     return hipGetLastError();
 }
 
+// 2 kap in FP32, rounded up
+static float reach_f32(double kap)
+{
+    float f = (float)(2.0 * kap);
+    return ((double)f < 2.0 * kap) ? std::nextafter(f, INFINITY) : f;
+}
+
 // fused: candidates at h0, Newton over candidates, exact lists at the new h.
-// Expects the packed positions of the cell build (h0 in them).
+// Expects the packed positions and walk records of the cell build (h0 in them).
 hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
                                 hipStream_t s, const Marks& mk, bool with_density)
 {
@@ -586,13 +615,15 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     // short reach first; the full-reach pair runs only if an h left it (the
     // kernels read the device flag and return at once when it is clear)
     const double lam = fmin(kFusedReach, P.kappa);
-    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk, W.cand, lam);
+    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand,
+                                                 lam, reach_f32(lam));
     mk.at(1, s);
     if (P.newton_iters > 0) {
         k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h, lam);
         if (lam < P.kappa) {
-            k_candidates_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nk,
-                                                              W.cand, P.kappa);
+            k_candidates_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
+                                                              W.nk, W.cand, P.kappa,
+                                                              reach_f32(P.kappa));
             k_update_h_list_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
                                                                  p->h, P.kappa);
         }

@@ -258,3 +258,44 @@ def test_fused_step_short_reach(name):
     nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, a["x"], a["y"], a["z"], h_o)
     assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
     assert np.array_equal(P, oracle_pairs(lists, gath))
+
+
+def _reach_counts(w, h0, factors):
+    """{f: per-particle number of b != a with r_ab < f max(h0_a, h0_b)} (minimum
+    images on periodic axes), by brute force in row chunks."""
+    a = w.arrays
+    p = w.params
+    X = np.stack([a["x"], a["y"], a["z"]], axis=1)
+    L = np.asarray(p["box_hi"]) - np.asarray(p["box_lo"])
+    per = np.asarray(p["periodic"], dtype=bool)
+    out = {f: np.zeros(w.n, np.int64) for f in factors}
+    for i0 in range(0, w.n, 256):
+        d = X[None, :, :] - X[i0:i0 + 256, None, :]
+        d = np.where(per, d - L * np.round(d / L), d)
+        q = np.sqrt(np.sum(d * d, axis=2)) / np.maximum(h0[i0:i0 + 256, None], h0[None, :])
+        q[np.arange(q.shape[0]), i0 + np.arange(q.shape[0])] = np.inf     # b != a
+        for f in factors:
+            out[f][i0:i0 + 256] = np.sum(q < f, axis=1)
+    return out
+
+
+@pytest.mark.parametrize("name", ["lattice12", "patch", "random"])
+def test_fused_candidates_cover_reach(name):
+    """The candidate walk of the fused step tests in FP32 with a widened reach:
+    its count for every target lies between the exact number of b != a with
+    r_ab < 2 lam max(h0_a, h0_b) and that number at a reach larger by a relative
+    1e-3, for lam the short reach 1.05 or, when the full-reach pass ran, kappa."""
+    w = CASES[name]()
+    cfg, _ = configs(w, ng_max=NG)
+    r = Run(w, cfg, _with_rho_ref(w))
+    sph.step(cfg, r.parts, r.g, r.ws)
+    assert r.status() == (0, 0)
+    nk_v, cap = sph.candidates_view(cfg, r.ws)
+    nk = np.empty(w.n, np.int64)
+    nk[r.ids()] = nk_v.cpu().numpy()
+    assert nk.max() <= cap
+    lams = sorted({min(1.05, cfg.h_ratio_max), cfg.h_ratio_max})
+    fs = [2 * l for l in lams] + [2 * l * (1 + 1e-3) for l in lams]
+    cnt = _reach_counts(w, w.arrays["h"], fs)
+    ok = [bool(np.all((cnt[2 * l] <= nk) & (nk <= cnt[2 * l * (1 + 1e-3)]))) for l in lams]
+    assert any(ok), name
