@@ -239,12 +239,37 @@ namespace sph {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kPiHalfSq = (kPi * kPi) / 4.0;
 
+// s t + c as one v_fma_f64 that takes the coefficient c from a scalar register
+// pair.  Written out because, left to itself, the compiler keeps polynomial
+// coefficients in vector registers and issues a copy before each step
+// (v_mov_b64 + v_fmac_f64), twice the vector instructions of the polynomial.
+SPH_DEV double fma_sc(double s, double t, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(s), "v"(t), "s"(c));
+    return r;
+}
+
+// 1/sqrt(x) for normal x > 0: the hardware estimate (relative error about
+// 2^-23) refined by two Newton steps on f(y) = 1/y^2 - x, each
+// y <- y + (y/2)(1 - x y^2), to within a few ulp.
+SPH_DEV double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 template <int K>
 SPH_DEV double horner(const double (&c)[K], double t)
 {
     double s = c[K - 1];
 #pragma unroll
-    for (int k = K - 2; k >= 0; --k) s = fma(s, t, c[k]);
+    for (int k = K - 2; k >= 0; --k) s = fma_sc(s, t, c[k]);
     return s;
 }
 
@@ -288,6 +313,9 @@ SPH_DEV double sinc_S(double t, int n)
 #endif
 #ifndef SPH_WAVES_PAIR
 #define SPH_WAVES_PAIR 2
+#endif
+#ifndef SPH_WAVES_IAD
+#define SPH_WAVES_IAD 3
 #endif
 #ifndef SPH_WAVES_SEARCH
 #define SPH_WAVES_SEARCH 3

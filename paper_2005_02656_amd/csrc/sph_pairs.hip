@@ -102,7 +102,7 @@ __device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, double c1
     return q;
 }
 
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_iad(Params P, Domain* __restrict__ dom,
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Params P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ list,
                                                 const Pos4* __restrict__ p4,
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             const double xv = -(vx * dx + vy * dy + vz * dz);
             double Pi = 0.0;
             if (xv < 0.0) {
-                const double w = xv / sqrt(r2);
+                const double w = xv * rsqrt_nr(r2);
                 const double vsig = ca + rb.c - 3.0 * w;
                 Pi = -0.5 * al * vsig * w;
             }
