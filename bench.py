@@ -67,10 +67,12 @@ def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True):
     return {
         # bbox (x y z h), keys, 8 radix passes over 8-byte keys and 4-byte indices,
         # permutation of the state (15 fields with the weakly compressible EOS,
-        # else 13, plus the id), cell table fill
-        "build_cells": 32 + 12 + 8 * 24 + (16 if wc else 14) * 16 + 32 + 8,
-        # p4 read, candidate list and count written (k_c candidates per particle)
-        "candidates": 32 + 4 + 4 * k_c,
+        # else 13, plus the id), packed positions (32 B) and FP32 walk records
+        # (16 B), cell table fill
+        "build_cells": 32 + 12 + 8 * 24 + (16 if wc else 14) * 16 + 32 + 16 + 8,
+        # p4 of the target and the FP32 walk records read, candidate list and
+        # count written (k_c candidates per particle)
+        "candidates": 32 + 16 + 4 + 4 * k_c,
         # p4 read, candidate list read once per iteration, h written
         "newton_h": 32 + 8 + 4 * k_c * iters,
         # p4 repack, candidates read, counts and the filtered list written, and
@@ -78,8 +80,11 @@ def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True):
         "lists": 64 + 4 + 4 * k_c + 8 + 4 * k_s + ((64 if wc else 48) if fused else 0),
         # separate density pass (stage path): p4 m u (p_ref rho_ref), list, 4 out
         "density": 0 if fused else (100 if wc else 84) + 4 * k_g,
-        "iad": 24 + 32 + 72 + 4 + 4 * k_g + 48 + 128,  # vol, p4, rec sources, list, C, records
-        "momentum_energy": 32 + 128 + 8 + 8 + 4 * k_s + 32,  # p4, record, u, counts, list, out
+        # volume pass: m rho p4 in, m/rho and {x y z m/rho} out; IAD pass: p4 of
+        # the target, {x y z m/rho} records, count and list, the record's other
+        # sources (m rho omega p c v), C and the 144-byte records out
+        "iad": (16 + 32 + 8 + 32) + 32 + 32 + 4 + 4 * k_g + 64 + 48 + 144,
+        "momentum_energy": 144 + 8 + 8 + 4 * k_s + 32,  # record, u, counts, list, out
         "integrate": 13 * 8 + 4 * 8 + 11 * 8,          # state + rates in, state out
     }[phase]
 

@@ -131,9 +131,9 @@ Params make_params(const sph_config* cfg, double bn, int lcap, int cand_cap)
         P.box_hi[k] = cfg->box_hi[k];
         P.L[k] = cfg->box_hi[k] - cfg->box_lo[k];
         P.halfL[k] = 0.5 * P.L[k];
-        P.Lf[k] = (float)P.L[k];
-        P.halfLf[k] = (float)P.halfL[k];
         P.periodic[k] = cfg->periodic[k] ? 1 : 0;
+        P.wrapL[k] = P.periodic[k] ? (float)P.L[k] : 0.0f;
+        P.wrapInvL[k] = P.periodic[k] ? (float)(1.0 / P.L[k]) : 0.0f;
     }
     P.sinc_n = (int)cfg->sinc_n;
     P.bn = bn;

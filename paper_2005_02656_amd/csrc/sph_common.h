@@ -41,7 +41,8 @@ struct Params {
     int lcap;              // largest admissible cell level (8^lcap <= table size)
     int precision;
     int cand_cap;          // candidate-list capacity of the fused step (0: off)
-    float Lf[3], halfLf[3];  // L and L/2 in FP32 (the fused step's candidate walk)
+    float wrapL[3], wrapInvL[3];  // L and 1/L in FP32 on periodic axes, 0 on open ones
+                                  // (the fused step's candidate walk)
 };
 
 // ---------------------------------------------------------------- device domain
@@ -332,7 +333,7 @@ SPH_DEV double sinc_S(double t, int n)
 #define SPH_MOM_ATTR SPH_WAVES_CAP(SPH_WAVES_MOM)
 #endif
 #ifndef SPH_WAVES_CAND
-#define SPH_WAVES_CAND 6
+#define SPH_WAVES_CAND 7
 #endif
 // the candidate walk runs best with exactly this many (registers held to fit):
 // its dependent cell-record -> particle-record round trips need resident

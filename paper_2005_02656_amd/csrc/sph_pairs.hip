@@ -86,11 +86,12 @@ struct RecSrc {
     const double *m, *rho, *omega, *p, *c, *vx, *vy, *vz, *h, *x, *y, *z;
 };
 
-__device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, double c11, double c12,
-                                           double c13, double c22, double c23, double c33)
+__device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, const Pos4& pa,
+                                           double c11, double c12, double c13, double c22,
+                                           double c23, double c33)
 {
     MomRec q;
-    q.x = R.x[a]; q.y = R.y[a]; q.z = R.z[a]; q.h = R.h[a];
+    q.x = pa.x; q.y = pa.y; q.z = pa.z; q.h = pa.h;
     q.c11 = c11; q.c12 = c12; q.c13 = c13; q.c22 = c22; q.c23 = c23; q.c33 = c33;
     const double r = R.rho[a];
     q.irho = 1.0 / r;
@@ -98,7 +99,7 @@ __device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, double c1
     q.pb = R.p[a] / (R.omega[a] * r * r);
     q.m = R.m[a];
     q.vx = R.vx[a]; q.vy = R.vy[a]; q.vz = R.vz[a];
-    q.invh = 1.0 / R.h[a];
+    q.invh = 1.0 / pa.h;
     return q;
 }
 
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
     }
     c11[a] = a11; c12[a] = a12; c13[a] = a13;
     c22[a] = a22; c23[a] = a23; c33[a] = a33;
-    if (rec) rec[a] = make_rec(R, a, a11, a12, a13, a22, a23, a33);
+    if (rec) rec[a] = make_rec(R, a, pa, a11, a12, a13, a22, a23, a33);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_rec(int64_t n, RecSrc R,
@@ -178,7 +179,9 @@ __global__ __launch_bounds__(kBlock) void k_pack_rec(int64_t n, RecSrc R,
                                                      MomRec* __restrict__ rec)
 {
     int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (a < n) rec[a] = make_rec(R, a, c11[a], c12[a], c13[a], c22[a], c23[a], c33[a]);
+    if (a < n)
+        rec[a] = make_rec(R, a, Pos4{R.x[a], R.y[a], R.z[a], R.h[a]}, c11[a], c12[a], c13[a],
+                          c22[a], c23[a], c33[a]);
 }
 
 struct MomOut {

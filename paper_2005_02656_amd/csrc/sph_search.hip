@@ -33,10 +33,6 @@ constexpr double kCullMargin = 1e-9;  // relative to the cell edge
 #ifndef SPH_CELL_ROW
 #define SPH_CELL_ROW 2
 #endif
-// 1: one 4-byte store per candidate instead of whole chunks from registers
-#ifndef SPH_CAND_DIRECT
-#define SPH_CAND_DIRECT 0
-#endif
 
 // spread the low 10 bits of v to every third bit (cell coordinates, level <= 9)
 __device__ __forceinline__ uint32_t spread10(uint32_t v)
@@ -321,12 +317,13 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 // factor of this pass), by the same per-target cell walk over 16-byte FP32
 // records.  The test runs in FP32 on offsets from the domain's low corner, with
 // the reach widened by a bound on their rounding: each offset is within
-// 2^-24 ext of its FP64 value (ext: the largest extent of the key domain) and
-// each difference or periodic shift rounds by at most as much again, so every
-// displacement component is within 5 * 2^-24 ext and the distance within
-// sqrt(3) times that, below the slack 2^-20 ext added to the reach; the factor
-// 1 + 2^-18 on the squared reach covers the FP32 rounding of r^2 and of the
-// reach itself.  The extras are at most a relative 1e-4 beyond the reach at
+// 2^-24 ext of its FP64 value (ext: the largest extent of the key domain); the
+// difference, the FP32 box length and the shift by it each add at most as much
+// again, and where d/L rounds across +-1/2 the other image is taken, at most
+// 2^-24 L farther.  Every displacement component is then within 6 * 2^-24 ext
+// and the distance within sqrt(3) times that, below the slack 2^-20 ext added
+// to the reach; the factor 1 + 2^-18 on the squared reach covers the FP32
+// rounding of r^2 and of the reach itself.  The extras are at most a relative 1e-4 beyond the reach at
 // the benchmark sizes, and the passes after this one test every candidate in
 // FP64.  (A wavefront walking the union of its 64 targets' stencils, with
 // scalar or LDS-staged particle loads, tested 2.4x more pairs and ran 1.6-2.1x
@@ -348,13 +345,11 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
     const double hmax0 = ord_value(D.hmax_new_bits);
     const int cap = P.cand_cap;
     const float slack = D.walk_slack;
+    // candidates are staged in LDS, column per lane, and written out in
+    // whole chunks of 8 (two 16-byte stores per lane)
+    __shared__ int32_t stage[8][kBlock];
+    const int t = threadIdx.x;
     int k = 0;
-    int32_t buf[8];
-    auto flush = [&](int j0) {
-        int4* dst = (int4*)(cand + lpos8(a, j0, cap));
-        dst[0] = make_int4(buf[0], buf[1], buf[2], buf[3]);
-        dst[1] = make_int4(buf[4], buf[5], buf[6], buf[7]);
-    };
     walk_cells(
         P, D, cells, pf, pa.x, pa.y, pa.z, 2.0 * kap * fmax((double)fa.h, hmax0),
         [&](const CellRange& cr, double g2) {
@@ -362,31 +357,30 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
             return g2 < hc * hc;
         },
         [&](int32_t b, const Pos4f& q) {
-            if (b == a) return;
+            // minimum image without branches: the shift is 0 on open axes
             float d[3] = {q.x - fa.x, q.y - fa.y, q.z - fa.z};
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                if (P.periodic[c]) {
-                    if (d[c] > P.halfLf[c]) d[c] -= P.Lf[c];
-                    else if (d[c] <= -P.halfLf[c]) d[c] += P.Lf[c];
-                }
+                d[c] = fmaf(-P.wrapL[c], rintf(d[c] * P.wrapInvL[c]), d[c]);
             const float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             const float R = k2f * fmaxf(fa.h, q.h) + slack;
-            if (r2 < (R * R) * (1.0f + 0x1p-18f)) {
+            if (r2 < (R * R) * (1.0f + 0x1p-18f) && b != a) {
                 if (k < cap) {
-#if SPH_CAND_DIRECT
-                    cand[lpos8(a, k, cap)] = b;
-#else
-                    buf[k & 7] = b;
-                    if ((k & 7) == 7) flush(k & ~7);
-#endif
+                    stage[k & 7][t] = b;
+                    if ((k & 7) == 7) {
+                        int4* dst = (int4*)(cand + lpos8(a, k & ~7, cap));
+                        dst[0] = make_int4(stage[0][t], stage[1][t], stage[2][t], stage[3][t]);
+                        dst[1] = make_int4(stage[4][t], stage[5][t], stage[6][t], stage[7][t]);
+                    }
                 }
                 ++k;
             }
         });
-#if !SPH_CAND_DIRECT
-    if (k < cap && (k & 7) != 0) flush(k & ~7);   // the partial last chunk
-#endif
+    if (k < cap && (k & 7) != 0) {   // the partial last chunk
+        int4* dst = (int4*)(cand + lpos8(a, k & ~7, cap));
+        dst[0] = make_int4(stage[0][t], stage[1][t], stage[2][t], stage[3][t]);
+        dst[1] = make_int4(stage[4][t], stage[5][t], stage[6][t], stage[7][t]);
+    }
     nk[a] = k;
     if (k > cap) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
 }
