@@ -132,6 +132,8 @@ Params make_params(const sph_config* cfg, double bn, int lcap, int cand_cap)
         P.L[k] = cfg->box_hi[k] - cfg->box_lo[k];
         P.halfL[k] = 0.5 * P.L[k];
         P.periodic[k] = cfg->periodic[k] ? 1 : 0;
+        P.wrapLd[k] = P.periodic[k] ? P.L[k] : 0.0;
+        P.wrapInvLd[k] = P.periodic[k] ? 1.0 / P.L[k] : 0.0;
         P.wrapL[k] = P.periodic[k] ? (float)P.L[k] : 0.0f;
         P.wrapInvL[k] = P.periodic[k] ? (float)(1.0 / P.L[k]) : 0.0f;
     }

@@ -41,8 +41,8 @@ struct Params {
     int lcap;              // largest admissible cell level (8^lcap <= table size)
     int precision;
     int cand_cap;          // candidate-list capacity of the fused step (0: off)
-    float wrapL[3], wrapInvL[3];  // L and 1/L in FP32 on periodic axes, 0 on open ones
-                                  // (the fused step's candidate walk)
+    double wrapLd[3], wrapInvLd[3];  // L and 1/L on periodic axes, 0 on open ones
+    float wrapL[3], wrapInvL[3];     // the same in FP32 (the fused step's candidate walk)
 };
 
 // ---------------------------------------------------------------- device domain
@@ -214,12 +214,16 @@ SPH_DEV uint32_t quantize(double x, double lo, double scale)
 SPH_DEV double disp(const Params& P, double xa, double ya, double za, double xb, double yb,
                     double zb, double& dx, double& dy, double& dz)
 {
+    // minimum image: d - L rint(d/L), a single rounding like d -= L, and no
+    // shift on open axes (L = 0 there).  It picks the image of the half-open
+    // (-L/2, L/2] everywhere except within rounding of |d| = L/2, where no
+    // pair is within reach (the step flags 4h >= L as an error).
     dx = xb - xa;
     dy = yb - ya;
     dz = zb - za;
-    if (P.periodic[0]) { if (dx > P.halfL[0]) dx -= P.L[0]; else if (dx <= -P.halfL[0]) dx += P.L[0]; }
-    if (P.periodic[1]) { if (dy > P.halfL[1]) dy -= P.L[1]; else if (dy <= -P.halfL[1]) dy += P.L[1]; }
-    if (P.periodic[2]) { if (dz > P.halfL[2]) dz -= P.L[2]; else if (dz <= -P.halfL[2]) dz += P.L[2]; }
+    dx = fma(-P.wrapLd[0], rint(dx * P.wrapInvLd[0]), dx);
+    dy = fma(-P.wrapLd[1], rint(dy * P.wrapInvLd[1]), dy);
+    dz = fma(-P.wrapLd[2], rint(dz * P.wrapInvLd[2]), dz);
     double r2 = dx * dx;
     r2 = r2 + dy * dy;
     r2 = r2 + dz * dz;
