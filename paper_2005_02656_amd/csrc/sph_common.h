@@ -327,8 +327,11 @@ SPH_DEV double sinc_S(double t, int n)
 #endif
 // exactly n wavefronts per SIMD (the compiler holds the registers to fit)
 #define SPH_WAVES_EXACT(n) __attribute__((amdgpu_waves_per_eu(n, n)))
+#ifndef SPH_WAVES_NEWTON
+#define SPH_WAVES_NEWTON 4
+#endif
 #ifndef SPH_NEWTON_ATTR
-#define SPH_NEWTON_ATTR SPH_WAVES_CAP(SPH_WAVES_SEARCH)
+#define SPH_NEWTON_ATTR SPH_WAVES_CAP(SPH_WAVES_NEWTON)
 #endif
 #ifndef SPH_FILTER_ATTR
 #define SPH_FILTER_ATTR SPH_WAVES_CAP(SPH_WAVES_SEARCH)

@@ -414,6 +414,42 @@ __device__ __forceinline__ void load_chunk(const int32_t* __restrict__ cand, int
 }
 
 // Newton iterations summing over the candidate list (self term added: S(0) = 1)
+// The two lanes of a pair (2q, 2q+1) swap a 32-bit value (quad permute 1 0 3 2).
+__device__ __forceinline__ int32_t pair_swap(int32_t v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double pair_swap(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)pair_swap((int32_t)(uint32_t)u);
+    const uint32_t hi = (uint32_t)pair_swap((int32_t)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// x, y, z of candidate b of this lane, gathered by the two lanes of a pair
+// together: one 16-byte load per lane fetches the even lane's record (x, y to
+// the even lane, z, h to the odd one) and a second the odd lane's, so the two
+// loads of a pair touch one line each instead of two per lane; a swap then
+// completes each lane's own position.  Both lanes of the pair must be active.
+__device__ __forceinline__ void pair_gather_xyz(const Pos4* __restrict__ p4, int32_t b, int odd,
+                                                double& x, double& y, double& z)
+{
+    const int32_t o = pair_swap(b);
+    const int32_t rA = odd ? o : b;   // the even lane's candidate
+    const int32_t rB = odd ? b : o;   // the odd lane's candidate
+    const double2* half = (const double2*)p4;
+    const double2 A = half[2 * (int64_t)rA + odd];
+    const double2 B = half[2 * (int64_t)rB + odd];
+    // even lane: A = (x, y) of its own record, B = (x, y) of the odd lane's;
+    // odd lane: A = (z, h) of the even lane's record, B = (z, h) of its own
+    const double r0 = pair_swap(odd ? A.x : B.x);
+    const double r1 = pair_swap(B.y);
+    x = odd ? r0 : A.x;
+    y = odd ? r1 : A.y;
+    z = odd ? B.x : r0;
+}
+
 __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restrict__ dom,
                                               const int32_t* __restrict__ nk,
                                               const int32_t* __restrict__ cand,
@@ -423,13 +459,18 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
-    const int64_t a = lb * kBlock + threadIdx.x;
-    if (a >= P.n) return;
+    // lanes past the end shadow the last particle with no candidates, so that
+    // both lanes of every pair run the gathers together
+    const int64_t a0 = lb * kBlock + threadIdx.x;
+    const bool live = a0 < P.n;
+    const int64_t a = live ? a0 : P.n - 1;
+    const int odd = threadIdx.x & 1;
     const Pos4 pa = p4[a];
     const double xa = pa.x, ya = pa.y, za = pa.z;
     const double h0 = pa.h;
     const int cap = P.cand_cap;
-    const int cnt = min(nk[a], cap);
+    const int cnt = live ? min(nk[a], cap) : 0;
+    const int cntp = max(cnt, pair_swap(cnt));   // the pair's trip count
     // the candidates reach 2 lam max(h0_a, h0_b): exact as long as every
     // iterate stays at or below lam h0 (2 (lam h0) == (2 lam) h0 in FP64)
     const double hlim = lam * h0;
@@ -440,15 +481,17 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
         const double R2 = h2 * h2;
         const double tsc = kPiHalfSq / (hc * hc);
         double sS = 1.0, sV = 0.0;
-        for (int j0 = 0; j0 < cnt; j0 += 8) {
+        for (int j0 = 0; j0 < cntp; j0 += 8) {
             int32_t bb[8];
-            load_chunk(cand, a, j0, cap, cnt, bb);
+            if (j0 < cnt) {
+                load_chunk(cand, a, j0, cap, cnt, bb);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) bb[u] = (int32_t)a;
+            }
             double qx[8], qy[8], qz[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const Pos4* q = p4 + bb[u];
-                qx[u] = q->x; qy[u] = q->y; qz[u] = q->z;
-            }
+            for (int u = 0; u < 8; ++u) pair_gather_xyz(p4, bb[u], odd, qx[u], qy[u], qz[u]);
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 double dx, dy, dz;
@@ -464,6 +507,7 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
         hc = newton_step(P, hc, h0, sS, sV);
         over = over || hc > hlim;
     }
+    if (!live) return;
     h[a] = hc;
     if (over) {
         // this h may have missed candidates; the full-reach pass recomputes it
