@@ -124,18 +124,23 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
     const double w0 = P.bn / (ha * ha * ha);
     const int cnt = min(nc[a], P.ng_max);
     double t11 = 0, t12 = 0, t13 = 0, t22 = 0, t23 = 0, t33 = 0;
-    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
-        int32_t bb[kBatch];
-        bool ok[kBatch];
+    // the next batch's list entries are fetched while this batch computes
+    int32_t nx[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            int32_t b = (j0 + u < cnt) ? list[lpos(a, j0 + u, P.ng_max)] : -1;
-            ok[u] = (uint32_t)b < (uint32_t)P.n;
-            bb[u] = ok[u] ? b : (int32_t)a;
-        }
+    for (int u = 0; u < kBatch; ++u) nx[u] = (u < cnt) ? list[lpos(a, u, P.ng_max)] : -1;
+    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+        bool ok[kBatch];
         PosV q[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) q[u] = pv[bb[u]];
+        for (int u = 0; u < kBatch; ++u) {
+            ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+            q[u] = pv[ok[u] ? nx[u] : (int32_t)a];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int j = j0 + kBatch + u;
+            nx[u] = (j < cnt) ? list[lpos(a, j, P.ng_max)] : -1;
+        }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             if (!ok[u]) continue;
@@ -218,22 +223,14 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
         constexpr int kMomBatch = SPH_MOM_BATCH;
-        // list entries and records of the batch starting at k0 (entries past
-        // the end read the target itself and are skipped)
-        auto load = [&](int k0, bool (&ok)[kMomBatch], bool (&gat)[kMomBatch],
-                        MomRec (&rbb)[kMomBatch]) {
-            int32_t bb[kMomBatch];
+        // list entries of the batch starting at k0 (-1 past the end)
+        auto entries = [&](int k0, int32_t (&e)[kMomBatch]) {
 #pragma unroll
             for (int u = 0; u < kMomBatch; ++u) {
                 const int k = k0 + u;
-                gat[u] = k < cg;
-                const int j = gat[u] ? k : ng - 1 - (k - cg);
-                int32_t b = (k < total) ? list[lpos(a, j, ng)] : -1;
-                ok[u] = (uint32_t)b < (uint32_t)P.n;
-                bb[u] = ok[u] ? b : (int32_t)a;
+                const int j = (k < cg) ? k : ng - 1 - (k - cg);
+                e[u] = (k < total) ? list[lpos(a, j, ng)] : -1;
             }
-#pragma unroll
-            for (int u = 0; u < kMomBatch; ++u) rbb[u] = rec[bb[u]];
         };
         auto pair = [&](bool gather, const MomRec& rb) {
             double dx, dy, dz;
@@ -273,13 +270,23 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             e1 += mb * (vx * Aax + vy * Aay + vz * Aaz);
             e2 += vx * gx + vy * gy + vz * gz;
         };
-        bool okA[kMomBatch], gatA[kMomBatch];
-        MomRec rA[kMomBatch];
+        // the records of a batch are gathered, then the next batch's list
+        // entries fetched while this batch computes (entries past the end read
+        // the target itself and are skipped)
+        int32_t nx[kMomBatch];
+        entries(0, nx);
         for (int k0 = 0; k0 < total; k0 += kMomBatch) {
-            load(k0, okA, gatA, rA);
+            bool ok[kMomBatch];
+            MomRec rb[kMomBatch];
+#pragma unroll
+            for (int u = 0; u < kMomBatch; ++u) {
+                ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+                rb[u] = rec[ok[u] ? nx[u] : (int32_t)a];
+            }
+            entries(k0 + kMomBatch, nx);
 #pragma unroll
             for (int u = 0; u < kMomBatch; ++u)
-                if (okA[u]) pair(gatA[u], rA[u]);
+                if (ok[u]) pair(k0 + u < cg, rb[u]);
         }
         const double du = pa_ * e1 + 0.5 * e2;
         O.ax[a] = axs;

@@ -413,6 +413,18 @@ __device__ __forceinline__ void load_chunk(const int32_t* __restrict__ cand, int
     for (int u = 0; u < 8; ++u) bb[u] = (j0 + u < cnt) ? v[u] : (int32_t)a;
 }
 
+// the chunk at j0, or the target itself in every entry when j0 >= cnt
+__device__ __forceinline__ void load_chunk_or_self(const int32_t* __restrict__ cand, int64_t a,
+                                                   int j0, int cap, int cnt, int32_t bb[8])
+{
+    if (j0 < cnt) {
+        load_chunk(cand, a, j0, cap, cnt, bb);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bb[u] = (int32_t)a;
+    }
+}
+
 // Newton iterations summing over the candidate list (self term added: S(0) = 1)
 // The two lanes of a pair (2q, 2q+1) swap a 32-bit value (quad permute 1 0 3 2).
 __device__ __forceinline__ int32_t pair_swap(int32_t v)
@@ -483,12 +495,7 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
         double sS = 1.0, sV = 0.0;
         for (int j0 = 0; j0 < cntp; j0 += 8) {
             int32_t bb[8];
-            if (j0 < cnt) {
-                load_chunk(cand, a, j0, cap, cnt, bb);
-            } else {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) bb[u] = (int32_t)a;
-            }
+            load_chunk_or_self(cand, a, j0, cap, cnt, bb);
             double qx[8], qy[8], qz[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) pair_gather_xyz(p4, bb[u], odd, qx[u], qy[u], qz[u]);
