@@ -354,7 +354,7 @@ SPH_DEV double sinc_S(double t, int n)
 #define SPH_WAVES_CAND_ATTR SPH_WAVES_CAP(SPH_WAVES_CAND)
 #endif
 #ifndef SPH_WAVES_MIXED
-#define SPH_WAVES_MIXED 2
+#define SPH_WAVES_MIXED 3
 #endif
 
 // Density, grad-h term and EOS of slot a from its two density sums

@@ -241,21 +241,25 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
     const float w0 = (float)(P.bn / (ha * ha * ha));
     const int cnt = min(nc[a], P.ng_max);
     double t11 = 0, t12 = 0, t13 = 0, t22 = 0, t23 = 0, t33 = 0;
-    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
-        int32_t bb[kBatch];
-        bool ok[kBatch];
+    // the next batch's list entries are fetched while this batch computes
+    int32_t nx[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int32_t b = (j0 + u < cnt) ? list[lpos(a, j0 + u, P.ng_max)] : -1;
-            ok[u] = (uint32_t)b < (uint32_t)P.n;
-            bb[u] = ok[u] ? b : (int32_t)a;
-        }
+    for (int u = 0; u < kBatch; ++u) nx[u] = (u < cnt) ? list[lpos(a, u, P.ng_max)] : -1;
+    for (int j0 = 0; j0 < cnt; j0 += kBatch) {
+        bool ok[kBatch];
         PosM q[kBatch];
         float vb[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            q[u] = pm[bb[u]];
-            vb[u] = vol[bb[u]];
+            ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+            const int32_t b = ok[u] ? nx[u] : (int32_t)a;
+            q[u] = pm[b];
+            vb[u] = vol[b];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int j = j0 + kBatch + u;
+            nx[u] = (j < cnt) ? list[lpos(a, j, P.ng_max)] : -1;
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -343,29 +347,34 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
         constexpr int kB = SPH_MOM_BATCH;
-        for (int k0 = 0; k0 < total; k0 += kB) {
-            int32_t bbv[kB];
-            bool okv[kB], gatv[kB];
+        // list entries of the batch starting at k0 (-1 past the end); the next
+        // batch's are fetched while this batch computes
+        auto entries = [&](int k0, int32_t (&e)[kB]) {
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
                 const int k = k0 + u;
-                gatv[u] = k < cg;
-                const int j = gatv[u] ? k : ng - 1 - (k - cg);
-                const int32_t b = (k < total) ? list[lpos(a, j, ng)] : -1;
-                okv[u] = (uint32_t)b < (uint32_t)P.n;
-                bbv[u] = okv[u] ? b : (int32_t)a;
+                const int j = (k < cg) ? k : ng - 1 - (k - cg);
+                e[u] = (k < total) ? list[lpos(a, j, ng)] : -1;
             }
+        };
+        int32_t nx[kB];
+        entries(0, nx);
+        for (int k0 = 0; k0 < total; k0 += kB) {
+            bool okv[kB];
             RecM rbv[kB];
             PosM qv[kB];
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
-                rbv[u] = rec[bbv[u]];
-                qv[u] = pm[bbv[u]];
+                okv[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+                const int32_t b = okv[u] ? nx[u] : (int32_t)a;
+                rbv[u] = rec[b];
+                qv[u] = pm[b];
             }
+            entries(k0 + kB, nx);
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
             if (!okv[u]) continue;
-            const bool gather = gatv[u];
+            const bool gather = k0 + u < cg;
             const RecM& rb = rbv[u];
             float dx, dy, dz;
             const float r2 = disp_m(g, pa, qv[u], dx, dy, dz);
