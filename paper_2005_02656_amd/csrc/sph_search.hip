@@ -462,6 +462,22 @@ __device__ __forceinline__ void pair_gather_xyz(const Pos4* __restrict__ p4, int
     z = odd ? B.x : r0;
 }
 
+// the whole record {x, y, z, h} of candidate b, gathered as above
+__device__ __forceinline__ Pos4 pair_gather_pos4(const Pos4* __restrict__ p4, int32_t b, int odd)
+{
+    const int32_t o = pair_swap(b);
+    const int32_t rA = odd ? o : b;
+    const int32_t rB = odd ? b : o;
+    const double2* half = (const double2*)p4;
+    const double2 A = half[2 * (int64_t)rA + odd];
+    const double2 B = half[2 * (int64_t)rB + odd];
+    // even lane: A = (x, y) own, B = (x, y) of the odd lane's record;
+    // odd lane: A = (z, h) of the even lane's record, B = (z, h) own
+    const double r0 = pair_swap(odd ? A.x : B.x);
+    const double r1 = pair_swap(odd ? A.y : B.y);
+    return odd ? Pos4{r0, r1, B.x, B.y} : Pos4{A.x, A.y, r0, r1};
+}
+
 __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restrict__ dom,
                                               const int32_t* __restrict__ nk,
                                               const int32_t* __restrict__ cand,
@@ -555,14 +571,19 @@ __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Dom
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
-    const int64_t a = lb * kBlock + threadIdx.x;
-    if (a >= P.n) return;
+    // lanes past the end shadow the last particle with no candidates, so that
+    // both lanes of every pair run the gathers together
+    const int64_t a0 = lb * kBlock + threadIdx.x;
+    const bool live = a0 < P.n;
+    const int64_t a = live ? a0 : P.n - 1;
+    const int odd = threadIdx.x & 1;
     const Pos4 pa = p4[a];
     const double xa = pa.x, ya = pa.y, za = pa.z, ha = pa.h;
     const double ha2 = 2.0 * ha;
     const double Ra2 = ha2 * ha2;
     const int cap = P.cand_cap;
-    const int cnt = min(nk[a], cap);
+    const int cnt = live ? min(nk[a], cap) : 0;
+    const int cntl = max(cnt, pair_swap(cnt));   // the pair's trip count
     const int ng = P.ng_max;
     const double tsc = kPiHalfSq / (ha * ha);
     double sS = 0.0, sD = 0.0;
@@ -571,14 +592,14 @@ __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Dom
         sD = 3.0 * O.m[a];
     }
     int cg = 0, co = 0;
-    for (int j0 = 0; j0 < cnt; j0 += 8) {
+    for (int j0 = 0; j0 < cntl; j0 += 8) {
         int32_t bb[8];
-        load_chunk(cand, a, j0, cap, cnt, bb);
+        load_chunk_or_self(cand, a, j0, cap, cnt, bb);
         Pos4 q[8];
         double mb[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            q[u] = p4[bb[u]];
+            q[u] = pair_gather_pos4(p4, bb[u], odd);
             if (kDens) mb[u] = O.m[bb[u]];
         }
 #pragma unroll
@@ -607,6 +628,7 @@ __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Dom
             }
         }
     }
+    if (!live) return;
     nc[a] = cg;
     ns[a] = cg + co;
     if (cg + co > ng) set_err(dom, SPH_ERRBIT_NEIGHBOR_OVERFLOW);
