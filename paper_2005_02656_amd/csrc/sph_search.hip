@@ -328,6 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 // FP64.  (A wavefront walking the union of its 64 targets' stencils, with
 // scalar or LDS-staged particle loads, tested 2.4x more pairs and ran 1.6-2.1x
 // slower at 64 M particles.)
+template <int kPer>   // bit k set: axis k periodic (the wrap is compiled out elsewhere)
 __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__ dom,
                                            const CellRange* __restrict__ cells,
                                            const Pos4* __restrict__ p4,
@@ -361,7 +362,7 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
             float d[3] = {q.x - fa.x, q.y - fa.y, q.z - fa.z};
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                d[c] = fmaf(-P.wrapL[c], rintf(d[c] * P.wrapInvL[c]), d[c]);
+                if (kPer & (1 << c)) d[c] = fmaf(-P.wrapL[c], rintf(d[c] * P.wrapInvL[c]), d[c]);
             const float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             const float R = k2f * fmaxf(fa.h, q.h) + slack;
             if (r2 < (R * R) * (1.0f + 0x1p-18f) && b != a) {
@@ -386,20 +387,58 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
 }
 
 // the short-reach pass, and the full-reach pass that runs only if flagged
+template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
     int32_t* __restrict__ cand, double kap, float k2f)
 {
-    candidates(P, dom, cells, p4, pf, nk, cand, kap, k2f);
+    candidates<kPer>(P, dom, cells, p4, pf, nk, cand, kap, k2f);
 }
+template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates_full(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
     int32_t* __restrict__ cand, double kap, float k2f)
 {
     if (dom->refit == 0u) return;
-    candidates(P, dom, cells, p4, pf, nk, cand, kap, k2f);
+    candidates<kPer>(P, dom, cells, p4, pf, nk, cand, kap, k2f);
+}
+
+// 2 kap in FP32, rounded up
+static float reach_f32(double kap)
+{
+    float f = (float)(2.0 * kap);
+    return ((double)f < 2.0 * kap) ? std::nextafter(f, INFINITY) : f;
+}
+
+// the candidate pass for the periodic axes of P
+template <int kPer>
+static void launch_candidates_per(bool full, const Params& P, const Ws& W, double kap,
+                                  hipStream_t s)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const float k2f = reach_f32(kap);
+    if (full)
+        k_candidates_full<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
+                                                                W.nk, W.cand, kap, k2f);
+    else
+        k_candidates<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf, W.nk,
+                                                           W.cand, kap, k2f);
+}
+static void launch_candidates(bool full, const Params& P, const Ws& W, double kap, hipStream_t s)
+{
+    const int per = (P.periodic[0] ? 1 : 0) | (P.periodic[1] ? 2 : 0) | (P.periodic[2] ? 4 : 0);
+    switch (per) {
+    case 0: launch_candidates_per<0>(full, P, W, kap, s); break;
+    case 1: launch_candidates_per<1>(full, P, W, kap, s); break;
+    case 2: launch_candidates_per<2>(full, P, W, kap, s); break;
+    case 3: launch_candidates_per<3>(full, P, W, kap, s); break;
+    case 4: launch_candidates_per<4>(full, P, W, kap, s); break;
+    case 5: launch_candidates_per<5>(full, P, W, kap, s); break;
+    case 6: launch_candidates_per<6>(full, P, W, kap, s); break;
+    default: launch_candidates_per<7>(full, P, W, kap, s); break;
+    }
 }
 
 // one chunk of 8 candidates of slot a (entries at or past cnt read as a itself)
@@ -674,12 +713,6 @@ hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
     return hipGetLastError();
 }
 
-// 2 kap in FP32, rounded up
-static float reach_f32(double kap)
-{
-    float f = (float)(2.0 * kap);
-    return ((double)f < 2.0 * kap) ? std::nextafter(f, INFINITY) : f;
-}
 
 // fused: candidates at h0, Newton over candidates, exact lists at the new h.
 // Expects the packed positions and walk records of the cell build (h0 in them).
@@ -694,15 +727,12 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     // short reach first; the full-reach pair runs only if an h left it (the
     // kernels read the device flag and return at once when it is clear)
     const double lam = fmin(kFusedReach, P.kappa);
-    k_candidates<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand,
-                                                 lam, reach_f32(lam));
+    launch_candidates(false, P, W, lam, s);
     mk.at(1, s);
     if (P.newton_iters > 0) {
         k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h, lam);
         if (lam < P.kappa) {
-            k_candidates_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
-                                                              W.nk, W.cand, P.kappa,
-                                                              reach_f32(P.kappa));
+            launch_candidates(true, P, W, P.kappa, s);
             k_update_h_list_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
                                                                  p->h, P.kappa);
         }
