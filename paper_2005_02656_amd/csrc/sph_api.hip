@@ -35,8 +35,10 @@ Layout make_layout(int64_t n, int ng_max)
     L.nc = take(sizeof(int32_t) * n);
     L.ns = take(sizeof(int32_t) * n);
     L.nk = take(sizeof(int32_t) * n);
-    L.p4 = take(sizeof(Pos4) * n);
-    L.pf = take(sizeof(Pos4f) * n);
+    // the cell walk loads whole batches past the end of a cell: both record
+    // arrays the walks read have kWalkPad spare entries after the last slot
+    L.p4 = take(sizeof(Pos4) * (n + kWalkPad));
+    L.pf = take(sizeof(Pos4f) * (n + kWalkPad));
     L.rec = take(sizeof(MomRec) * n);
     L.vol = take(sizeof(double) * n);
     L.pv = take(sizeof(PosV) * n);

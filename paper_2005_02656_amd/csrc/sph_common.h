@@ -22,6 +22,7 @@ constexpr int kMaxLevel = 9;         // cell table holds at most 8^9 cells
 constexpr int kKeyBits = 21;         // bits per axis in the 63-bit key
 constexpr int kSumBlocks = 1024;     // fixed partition of the conservation sums
 constexpr int kMaxPermFields = 16;
+constexpr int kWalkPad = 8;          // spare records after the last slot (cell-walk batches)
 
 // ---------------------------------------------------------------- run parameters
 // POD copied by value into every kernel.

@@ -25,11 +25,14 @@ namespace {
 
 constexpr double kCullMargin = 1e-9;  // relative to the cell edge
 
-// particle records of one cell loaded together by the cell walk, and cell
+// particle records of one cell loaded together by the cell walk (a batch may
+// read up to kCellBatch - 1 records past the cell's end: the record arrays keep
+// kWalkPad spare entries), and cell
 // records of one row (along z) loaded together
 #ifndef SPH_CELL_BATCH
 #define SPH_CELL_BATCH 2
 #endif
+static_assert(SPH_CELL_BATCH - 1 <= kWalkPad, "cell-walk batch overruns the record padding");
 #ifndef SPH_CELL_ROW
 #define SPH_CELL_ROW 2
 #endif
@@ -169,7 +172,7 @@ __device__ __forceinline__ void walk_cells(const Params& P, const Domain& D,
                     for (int32_t b0 = cr[i].s; b0 < e; b0 += kCellBatch) {
                         Rec q[kCellBatch];
 #pragma unroll
-                        for (int u = 0; u < kCellBatch; ++u) q[u] = recs[min(b0 + u, e - 1)];
+                        for (int u = 0; u < kCellBatch; ++u) q[u] = recs[b0 + u];
 #pragma unroll
                         for (int u = 0; u < kCellBatch; ++u)
                             if (b0 + u < e) body(b0 + u, q[u]);
@@ -350,6 +353,11 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
     // whole chunks of 8 (two 16-byte stores per lane)
     __shared__ int32_t stage[8][kBlock];
     const int t = threadIdx.x;
+    const int32_t self = (int32_t)a;
+    // r < 2 kap max(h_a, h_b) (+ slack) as r^2 < Ra^2 or r^2 < Rb^2
+    constexpr float kGrow = 1.0f + 0x1p-18f;
+    const float Ra = fmaf(k2f, fa.h, slack);
+    const float Ra2 = (Ra * Ra) * kGrow;
     int k = 0;
     walk_cells(
         P, D, cells, pf, pa.x, pa.y, pa.z, 2.0 * kap * fmax((double)fa.h, hmax0),
@@ -364,8 +372,9 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
             for (int c = 0; c < 3; ++c)
                 if (kPer & (1 << c)) d[c] = fmaf(-P.wrapL[c], rintf(d[c] * P.wrapInvL[c]), d[c]);
             const float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            const float R = k2f * fmaxf(fa.h, q.h) + slack;
-            if (r2 < (R * R) * (1.0f + 0x1p-18f) && b != a) {
+            const float Rb = fmaf(k2f, q.h, slack);
+            const bool near = (r2 < Ra2) | (r2 < (Rb * Rb) * kGrow);   // both evaluated
+            if (near & (b != self)) {
                 if (k < cap) {
                     stage[k & 7][t] = b;
                     if ((k & 7) == 7) {
