@@ -299,3 +299,27 @@ def test_fused_candidates_cover_reach(name):
     cnt = _reach_counts(w, w.arrays["h"], fs)
     ok = [bool(np.all((cnt[2 * l] <= nk) & (nk <= cnt[2 * l * (1 + 1e-3)]))) for l in lams]
     assert any(ok), name
+
+
+@pytest.mark.parametrize("per", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1),
+                                 (1, 0, 1), (0, 1, 1)])
+def test_fused_step_periodic_patterns(per):
+    """The candidate walk is compiled once per pattern of periodic axes; every
+    pattern gives the oracle's h, lists and density (the all-periodic pattern is
+    covered by the cases above)."""
+    w0 = inputs.random_periodic(1500, seed=9, h_lo=0.08, h_hi=0.10)
+    w = inputs.Workload(w0.name, w0.arrays, {**w0.params, "periodic": per})
+    cfg, ocfg = configs(w, ng_max=NG)
+    a = w.arrays
+    r = Run(w, cfg)
+    sph.step(cfg, r.parts, r.g, r.ws)
+    assert r.status() == (0, 0)
+    h_o = oracle.update_h(ocfg, a["x"], a["y"], a["z"], a["h"])
+    assert rel_err(r.by_id("h"), h_o) < TOL
+    P, nc, ns = r.neighbor_pairs()
+    nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, a["x"], a["y"], a["z"], h_o)
+    assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
+    assert np.array_equal(P, oracle_pairs(lists, gath))
+    rho_o, om_o, _, _ = oracle.density(ocfg, a["x"], a["y"], a["z"], h_o, a["m"], a["u"])
+    assert rel_err(r.by_id("rho"), rho_o) < TOL
+    assert rel_err(r.by_id("omega"), om_o) < TOL
