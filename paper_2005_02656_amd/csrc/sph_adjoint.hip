@@ -107,7 +107,7 @@ SPH_DEV void horner_d(const double (&c)[K], double t, double& p, double& dp)
 #pragma unroll
     for (int k = K - 2; k >= 0; --k) {
         dp = fma(dp, t, p);
-        p = fma(p, t, c[k]);
+        p = fma_sc(p, t, c[k]);
     }
 }
 
@@ -185,10 +185,10 @@ SPH_DEV void mom_pair_bwd(const Params& P, const double d[3], double r2, double 
     const double vab[3] = {A.vx - B.vx, A.vy - B.vy, A.vz - B.vz};
     const double xv = -(vab[0] * d[0] + vab[1] * d[1] + vab[2] * d[2]);
     const bool av = xv < 0.0;
-    double Pi = 0.0, w = 0.0, r = 1.0;
+    double Pi = 0.0, w = 0.0, ir = 1.0;   // ir = 1/r
     if (av) {
-        r = sqrt(r2);
-        w = xv / r;
+        ir = rsqrt_nr(r2);
+        w = xv * ir;
         Pi = -0.5 * P.alpha * (A.c + B.c - 3.0 * w) * w;
     }
     const double mb = B.m;
@@ -225,12 +225,12 @@ SPH_DEV void mom_pair_bwd(const Params& P, const double d[3], double r2, double 
         const double Pib = 0.5 * mb * (A.irho * gA + B.irho * gB);
         cbar = Pib * (-0.5 * P.alpha * w);
         const double wb = Pib * (-0.5 * P.alpha) * (A.c + B.c - 6.0 * w);
-        const double xvb = wb / r;          // w = xv / r
-        const double rbar = -wb * xv / (r * r);
+        const double xvb = wb * ir;          // w = xv / r
+        const double rbar = -wb * xv * (ir * ir);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             vabb[k] -= xvb * d[k];          // xv = -vab . d
-            db[k] += -xvb * vab[k] + rbar * d[k] / r;
+            db[k] += -xvb * vab[k] + rbar * d[k] * ir;
         }
     }
     if (kToA) {
@@ -319,7 +319,12 @@ struct MomFwd {
     const double *rho, *omega, *c, *u, *vol;
 };
 
-__global__ __launch_bounds__(kBlock) void k_adj_momentum(Params P, const int32_t* __restrict__ nc,
+// two wavefronts per SIMD: the pair's reverse terms fit 256 registers without
+// spills, and at one wavefront the gathers' latency went unhidden
+#ifndef SPH_ADJ_MOM_ATTR
+#define SPH_ADJ_MOM_ATTR SPH_WAVES_EXACT(2)
+#endif
+__global__ __launch_bounds__(kBlock) SPH_ADJ_MOM_ATTR void k_adj_momentum(Params P, const int32_t* __restrict__ nc,
                                                          const int32_t* __restrict__ ns,
                                                          const int32_t* __restrict__ list,
                                                          MomFwd F, Adj J)
@@ -329,8 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_momentum(Params P, const int32_t
     if (lb < 0) return;
     const int64_t i = lb * kBlock + threadIdx.x;
     if (i >= P.n) return;
-    const Pos4 qi = F.p4[i];
-    const MomRec ri = F.rec[i];
+    const MomRec ri = F.rec[i];   // the record holds the position and h
     const RateBar bi = J.rate[i];
     MomAcc acc = {};
     const int ng = P.ng_max;
@@ -348,12 +352,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_momentum(Params P, const int32_t
             ok[u] = (uint32_t)j < (uint32_t)P.n;
             jj[u] = ok[u] ? j : (int32_t)i;
         }
-        Pos4 qj[kB];
         MomRec rj[kB];
         RateBar bj[kB];
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
-            qj[u] = F.p4[jj[u]];
             rj[u] = F.rec[jj[u]];
             bj[u] = J.rate[jj[u]];
         }
@@ -361,10 +363,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_momentum(Params P, const int32_t
         for (int u = 0; u < kB; ++u) {
             if (!ok[u]) continue;
             double d[3];
-            const double r2 = disp(P, qi.x, qi.y, qi.z, qj[u].x, qj[u].y, qj[u].z, d[0], d[1], d[2]);
+            const double r2 = disp(P, ri.x, ri.y, ri.z, rj[u].x, rj[u].y, rj[u].z, d[0], d[1], d[2]);
             double Wi, dWi, Wj, dWj;
-            kernel_w(P, r2, qi.h, Wi, dWi);   // nonzero iff j in N(i)
-            kernel_w(P, r2, qj[u].h, Wj, dWj);
+            kernel_w(P, r2, ri.h, Wi, dWi);   // nonzero iff j in N(i)
+            kernel_w(P, r2, rj[u].h, Wj, dWj);
             // pair (i, j): i the target
             mom_pair_bwd<true>(P, d, r2, Wi, dWi, Wj, dWj, ri, rj[u], bi, acc);
             // pair (j, i): i the neighbour, displacement x_i - x_j
