@@ -263,6 +263,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
+#pragma clang fp contract(fast)
             if (!ok[u]) continue;
             float dx, dy, dz;
             const float r2 = disp_m(g, pa, q[u], dx, dy, dz);
@@ -373,6 +374,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
             entries(k0 + kB, nx);
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
+#pragma clang fp contract(fast)
             if (!okv[u]) continue;
             const bool gather = k0 + u < cg;
             const RecM& rb = rbv[u];

@@ -13,6 +13,12 @@
 namespace sph {
 namespace {
 
+// 1: the IAD and momentum pair terms may fuse multiply-adds
+#ifndef SPH_PAIR_CONTRACT
+#define SPH_PAIR_CONTRACT 1
+#endif
+
+
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_density(Params P, Domain* __restrict__ dom,
                                                     const int32_t* __restrict__ nc,
                                                     const int32_t* __restrict__ list,
@@ -143,6 +149,9 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
+#if SPH_PAIR_CONTRACT
+#pragma clang fp contract(fast)
+#endif
             if (!ok[u]) continue;
             double dx, dy, dz;
             double r2 = disp(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
@@ -233,6 +242,11 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             }
         };
         auto pair = [&](bool gather, const MomRec& rb) {
+#if SPH_PAIR_CONTRACT
+            // the pair terms may fuse multiply-adds (rounding-level changes
+            // only); r^2 itself comes from disp(), which never contracts
+#pragma clang fp contract(fast)
+#endif
             double dx, dy, dz;
             double r2 = disp(P, xa, ya, za, rb.x, rb.y, rb.z, dx, dy, dz);
             double Wa = 0.0;
