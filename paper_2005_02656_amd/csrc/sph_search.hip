@@ -248,16 +248,18 @@ __global__ void k_hmax_begin(Domain* d)
 }
 
 // largest h per cell (for the symmetric search) and overall
+// (h is read from the slot-ordered array: consecutive cells read consecutive
+// runs of it)
 __global__ __launch_bounds__(kBlock) void k_cells_hmax(Params P, Domain* __restrict__ dom,
                                                        CellRange* __restrict__ cells,
-                                                       const Pos4* __restrict__ p4, int64_t cap)
+                                                       const double* __restrict__ h, int64_t cap)
 {
     int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     int64_t ncell = int64_t(1) << (3 * dom->level);
     double hm = 0.0;
     if (c < ncell && c < cap) {
         const CellRange cr = cells[c];
-        for (int32_t b = cr.s; b < cr.e; ++b) hm = fmax(hm, p4[b].h);
+        for (int32_t b = cr.s; b < cr.e; ++b) hm = fmax(hm, h[b]);
         cells[c].hmax = hm;
     }
     for (int o = 32; o > 0; o >>= 1) hm = fmax(hm, __shfl_xor(hm, o, 64));
@@ -716,7 +718,7 @@ hipError_t launch_find_neighbors(const Params& P, const Layout& L, const Ws& W,
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
-    k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, L.ncells_cap);
+    k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, p->h, L.ncells_cap);
     k_find_neighbors<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.nc, W.ns,
                                                      W.list);
     return hipGetLastError();
@@ -731,7 +733,7 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
-    k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, L.ncells_cap);
+    k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, p->h, L.ncells_cap);
     mk.at(0, s);
     // short reach first; the full-reach pair runs only if an h left it (the
     // kernels read the device flag and return at once when it is clear)
