@@ -208,7 +208,6 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
                                                             const int32_t* __restrict__ list,
-                                                            const Pos4* __restrict__ p4,
                                                             const MomRec* __restrict__ rec,
                                                             const double* __restrict__ u,
                                                             MomOut O)
@@ -386,8 +385,8 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
     }
     MomOut O{p->ax, p->ay, p->az, p->du};
     k_dtmin_begin<<<1, 1, 0, s>>>(W.dom);
-    k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, W.p4, W.rec,
-                                                      p->u, O);
+    k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, W.rec, p->u,
+                                                      O);
     return hipGetLastError();
 }
 
