@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sph.h"
 
 namespace sph {
@@ -229,6 +231,42 @@ SPH_DEV double disp(const Params& P, double xa, double ya, double za, double xb,
     r2 = r2 + dy * dy;
     r2 = r2 + dz * dz;
     return r2;
+}
+
+// disp() with the minimum image applied on the axes of kPer only (bit k: axis
+// k periodic); on the others it is the identity there too, so the results are
+// the same bits as disp()'s
+template <int kPer>
+SPH_DEV double disp_p(const Params& P, double xa, double ya, double za, double xb, double yb,
+                      double zb, double& dx, double& dy, double& dz)
+{
+    dx = xb - xa;
+    dy = yb - ya;
+    dz = zb - za;
+    if (kPer & 1) dx = fma(-P.wrapLd[0], rint(dx * P.wrapInvLd[0]), dx);
+    if (kPer & 2) dy = fma(-P.wrapLd[1], rint(dy * P.wrapInvLd[1]), dy);
+    if (kPer & 4) dz = fma(-P.wrapLd[2], rint(dz * P.wrapInvLd[2]), dz);
+    double r2 = dx * dx;
+    r2 = r2 + dy * dy;
+    r2 = r2 + dz * dz;
+    return r2;
+}
+
+// calls f(std::integral_constant<int, kPer>) for the periodic axes of P
+template <class F>
+inline void with_periodic(const Params& P, F&& f)
+{
+    const int per = (P.periodic[0] ? 1 : 0) | (P.periodic[1] ? 2 : 0) | (P.periodic[2] ? 4 : 0);
+    switch (per) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    default: f(std::integral_constant<int, 7>{}); break;
+    }
 }
 
 // ------------------------------------------------------------- sinc kernel

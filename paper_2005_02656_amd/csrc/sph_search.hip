@@ -424,32 +424,19 @@ static float reach_f32(double kap)
 }
 
 // the candidate pass for the periodic axes of P
-template <int kPer>
-static void launch_candidates_per(bool full, const Params& P, const Ws& W, double kap,
-                                  hipStream_t s)
+static void launch_candidates(bool full, const Params& P, const Ws& W, double kap, hipStream_t s)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const float k2f = reach_f32(kap);
-    if (full)
-        k_candidates_full<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
-                                                                W.nk, W.cand, kap, k2f);
-    else
-        k_candidates<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf, W.nk,
-                                                           W.cand, kap, k2f);
-}
-static void launch_candidates(bool full, const Params& P, const Ws& W, double kap, hipStream_t s)
-{
-    const int per = (P.periodic[0] ? 1 : 0) | (P.periodic[1] ? 2 : 0) | (P.periodic[2] ? 4 : 0);
-    switch (per) {
-    case 0: launch_candidates_per<0>(full, P, W, kap, s); break;
-    case 1: launch_candidates_per<1>(full, P, W, kap, s); break;
-    case 2: launch_candidates_per<2>(full, P, W, kap, s); break;
-    case 3: launch_candidates_per<3>(full, P, W, kap, s); break;
-    case 4: launch_candidates_per<4>(full, P, W, kap, s); break;
-    case 5: launch_candidates_per<5>(full, P, W, kap, s); break;
-    case 6: launch_candidates_per<6>(full, P, W, kap, s); break;
-    default: launch_candidates_per<7>(full, P, W, kap, s); break;
-    }
+    with_periodic(P, [&](auto per) {
+        constexpr int kPer = decltype(per)::value;
+        if (full)
+            k_candidates_full<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
+                                                                    W.nk, W.cand, kap, k2f);
+        else
+            k_candidates<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
+                                                               W.nk, W.cand, kap, k2f);
+    });
 }
 
 // one chunk of 8 candidates of slot a (entries at or past cnt read as a itself)
@@ -528,6 +515,7 @@ __device__ __forceinline__ Pos4 pair_gather_pos4(const Pos4* __restrict__ p4, in
     return odd ? Pos4{r0, r1, B.x, B.y} : Pos4{A.x, A.y, r0, r1};
 }
 
+template <int kPer>
 __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restrict__ dom,
                                               const int32_t* __restrict__ nk,
                                               const int32_t* __restrict__ cand,
@@ -568,7 +556,7 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 double dx, dy, dz;
-                double r2 = disp(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
+                double r2 = disp_p<kPer>(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
                 if (j0 + u < cnt && r2 < R2) {
                     double S, vdS;
                     sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
@@ -590,26 +578,28 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
     }
 }
 
+template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
     double lam)
 {
-    update_h_list(P, dom, nk, cand, p4, h, lam);
+    update_h_list<kPer>(P, dom, nk, cand, p4, h, lam);
 }
+template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list_full(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
     double lam)
 {
     if (dom->refit == 0u) return;
-    update_h_list(P, dom, nk, cand, p4, h, lam);
+    update_h_list<kPer>(P, dom, nk, cand, p4, h, lam);
 }
 
 // exact lists from the candidates with the final h (same layout as k_find_neighbors)
 // kDens: also the density sums over the gather members (the same order as the
 // density pass over the gather list), then rho, Omega and the EOS
-template <bool kDens>
+template <bool kDens, int kPer>
 __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Domain* __restrict__ dom,
                                                    const int32_t* __restrict__ nk,
                                                    const int32_t* __restrict__ cand,
@@ -657,7 +647,7 @@ __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Dom
             if (j0 + u >= cnt) continue;
             const int32_t b = bb[u];
             double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
+            double r2 = disp_p<kPer>(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
             if (r2 < Ra2) {
                 if (cg < ng) {
                     list[lpos(a, cg, ng)] = b;
@@ -741,23 +731,33 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     launch_candidates(false, P, W, lam, s);
     mk.at(1, s);
     if (P.newton_iters > 0) {
-        k_update_h_list<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, p->h, lam);
+        with_periodic(P, [&](auto per) {
+            constexpr int kPer = decltype(per)::value;
+            k_update_h_list<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
+                                                                  p->h, lam);
+        });
         if (lam < P.kappa) {
             launch_candidates(true, P, W, P.kappa, s);
-            k_update_h_list_full<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
-                                                                 p->h, P.kappa);
+            with_periodic(P, [&](auto per) {
+                constexpr int kPer = decltype(per)::value;
+                k_update_h_list_full<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(
+                    P, W.dom, W.nk, W.cand, W.p4, p->h, P.kappa);
+            });
         }
     }
     mk.at(2, s);
     hipError_t e = launch_pack_p4(P, W, p, s);
     if (e != hipSuccess) return e;
     const DensOut O{p->m, p->u, p->p_ref, p->rho_ref, p->rho, p->omega, p->p, p->c};
-    if (with_density)
-        k_filter<true><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns,
-                                                       W.list, O);
-    else
-        k_filter<false><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns,
-                                                        W.list, O);
+    with_periodic(P, [&](auto per) {
+        constexpr int kPer = decltype(per)::value;
+        if (with_density)
+            k_filter<true, kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
+                                                                 W.nc, W.ns, W.list, O);
+        else
+            k_filter<false, kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
+                                                                  W.nc, W.ns, W.list, O);
+    });
     return hipGetLastError();
 }
 
