@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_back(PermSet S,
                                                          const uint64_t* __restrict__ tmp,
                                                          int64_t n, const Domain* __restrict__ dom,
                                                          Pos4* __restrict__ p4,
-                                                         Pos4f* __restrict__ pf)
+                                                         Pos4f* __restrict__ pf, float k2s)
 {
     int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
@@ -391,9 +391,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_back(PermSet S,
     q.z = __builtin_bit_cast(double, tmp[2 * n + i]);
     q.h = __builtin_bit_cast(double, tmp[9 * n + i]);
     p4[i] = q;
-    if (pf)
+    if (pf) {
+        const float R = fmaf(k2s, float_up(q.h), dom->walk_slack);
         pf[i] = Pos4f{(float)(q.x - dom->lo[0]), (float)(q.y - dom->lo[1]),
-                      (float)(q.z - dom->lo[2]), float_up(q.h)};
+                      (float)(q.z - dom->lo[2]), (R * R) * kWalkGrow};
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_p4(const double* __restrict__ x,
@@ -458,7 +460,8 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
         if (f) S.f[S.nf++] = f;
     k_gather<<<grid_xcd(nb), kBlock, 0, s>>>(S, W.idx0, (uint64_t*)W.tmp, n);
     k_scatter_back<<<nb, kBlock, 0, s>>>(S, (const uint64_t*)W.tmp, n, W.dom, W.p4,
-                                         P.cand_cap > 0 ? W.pf : nullptr);
+                                         P.cand_cap > 0 ? W.pf : nullptr,
+                                         short_reach_f32(P.kappa));
     return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include <type_traits>
@@ -75,11 +76,13 @@ struct alignas(32) Pos4 {
     double x, y, z, h;
 };
 // the candidate walk's record (fused step): FP32 offsets of the position from
-// the key domain's low corner and h rounded up; the walk widens its test to
-// cover their rounding, so its candidates are a superset of the exact ones
+// the key domain's low corner and the particle's squared short reach, widened
+// to cover the rounding of the FP32 test ((2 lambda h + slack)^2 (1 + 2^-18),
+// h rounded up), so the walk's candidates are a superset of the exact ones
 struct alignas(16) Pos4f {
-    float x, y, z, h;
+    float x, y, z, r2;
 };
+constexpr float kWalkGrow = 1.0f + 0x1p-18f;
 // what the IAD pass needs of a neighbour: position and volume m/rho
 struct alignas(32) PosV {
     double x, y, z, v;
@@ -131,6 +134,18 @@ constexpr double kFusedKappaMax = 1.25;
 #define SPH_FUSED_REACH 1.05
 #endif
 constexpr double kFusedReach = SPH_FUSED_REACH;
+
+// 2 kap in FP32, rounded up (host side)
+inline float reach_f32(double kap)
+{
+    float f = (float)(2.0 * kap);
+    return ((double)f < 2.0 * kap) ? nextafterf(f, INFINITY) : f;
+}
+// the same for the fused step's short reach lambda = min(kFusedReach, kappa)
+inline float short_reach_f32(double kappa)
+{
+    return reach_f32(kappa < kFusedReach ? kappa : kFusedReach);
+}
 int candidate_capacity(int ng_max);
 
 // ---------------------------------------------------------------- workspace layout

@@ -321,7 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 // Candidates: every b != a with r^2 < (2 kap max(h0_a, h0_b))^2 (kap: the reach
 // factor of this pass), by the same per-target cell walk over 16-byte FP32
 // records.  The test runs in FP32 on offsets from the domain's low corner, with
-// the reach widened by a bound on their rounding: each offset is within
+// the reach widened by a bound on their rounding (the cell build stores each
+// particle's widened squared reach in its record): each offset is within
 // 2^-24 ext of its FP64 value (ext: the largest extent of the key domain); the
 // difference, the FP32 box length and the shift by it each add at most as much
 // again, and where d/L rounds across +-1/2 the other image is taken, at most
@@ -333,12 +334,12 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 // FP64.  (A wavefront walking the union of its 64 targets' stencils, with
 // scalar or LDS-staged particle loads, tested 2.4x more pairs and ran 1.6-2.1x
 // slower at 64 M particles.)
-template <int kPer>   // bit k set: axis k periodic (the wrap is compiled out elsewhere)
+template <int kPer, bool kFull>   // bit k of kPer set: axis k periodic
 __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__ dom,
                                            const CellRange* __restrict__ cells,
                                            const Pos4* __restrict__ p4,
                                            const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-                                           int32_t* __restrict__ cand, double kap, float k2f)
+                                           int32_t* __restrict__ cand, double kap, float sc)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
@@ -350,21 +351,16 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
     const Pos4f fa = pf[a];
     const double hmax0 = ord_value(D.hmax_new_bits);
     const int cap = P.cand_cap;
-    const float slack = D.walk_slack;
     // candidates are staged in LDS, column per lane, and written out in
     // whole chunks of 8 (two 16-byte stores per lane)
     __shared__ int32_t stage[8][kBlock];
     const int t = threadIdx.x;
     const int32_t self = (int32_t)a;
-    // r < 2 kap max(h_a, h_b) (+ slack) as r^2 < Ra^2 or r^2 < Rb^2
-    constexpr float kGrow = 1.0f + 0x1p-18f;
-    const float Ra = fmaf(k2f, fa.h, slack);
-    const float Ra2 = (Ra * Ra) * kGrow;
     int k = 0;
     walk_cells(
-        P, D, cells, pf, pa.x, pa.y, pa.z, 2.0 * kap * fmax((double)fa.h, hmax0),
+        P, D, cells, pf, pa.x, pa.y, pa.z, 2.0 * kap * fmax(pa.h, hmax0),
         [&](const CellRange& cr, double g2) {
-            double hc = 2.0 * kap * fmax((double)fa.h, cr.hmax);
+            double hc = 2.0 * kap * fmax(pa.h, cr.hmax);
             return g2 < hc * hc;
         },
         [&](int32_t b, const Pos4f& q) {
@@ -374,8 +370,11 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
             for (int c = 0; c < 3; ++c)
                 if (kPer & (1 << c)) d[c] = fmaf(-P.wrapL[c], rintf(d[c] * P.wrapInvL[c]), d[c]);
             const float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            const float Rb = fmaf(k2f, q.h, slack);
-            const bool near = (r2 < Ra2) | (r2 < (Rb * Rb) * kGrow);   // both evaluated
+            // r < 2 kap max(h_a, h_b) (+ slack): r^2 below either widened
+            // squared reach (the full pass scales the short ones up by sc)
+            bool near;
+            if (kFull) near = (r2 < fa.r2 * sc) | (r2 < q.r2 * sc);
+            else near = (r2 < fa.r2) | (r2 < q.r2);
             if (near & (b != self)) {
                 if (k < cap) {
                     stage[k & 7][t] = b;
@@ -402,40 +401,38 @@ template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-    int32_t* __restrict__ cand, double kap, float k2f)
+    int32_t* __restrict__ cand, double kap, float sc)
 {
-    candidates<kPer>(P, dom, cells, p4, pf, nk, cand, kap, k2f);
+    candidates<kPer, false>(P, dom, cells, p4, pf, nk, cand, kap, sc);
 }
 template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates_full(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-    int32_t* __restrict__ cand, double kap, float k2f)
+    int32_t* __restrict__ cand, double kap, float sc)
 {
     if (dom->refit == 0u) return;
-    candidates<kPer>(P, dom, cells, p4, pf, nk, cand, kap, k2f);
-}
-
-// 2 kap in FP32, rounded up
-static float reach_f32(double kap)
-{
-    float f = (float)(2.0 * kap);
-    return ((double)f < 2.0 * kap) ? std::nextafter(f, INFINITY) : f;
+    candidates<kPer, true>(P, dom, cells, p4, pf, nk, cand, kap, sc);
 }
 
 // the candidate pass for the periodic axes of P
 static void launch_candidates(bool full, const Params& P, const Ws& W, double kap, hipStream_t s)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    const float k2f = reach_f32(kap);
+    // the records hold the squared short reach; the full pass scales it by
+    // at least (kap / lambda)^2 (the slack scales with it, which only widens)
+    const double lam = fmin(kFusedReach, P.kappa);
+    const double q = (kap / lam) * (kap / lam) * (1.0 + 0x1p-20);
+    float sc = (float)q;
+    if ((double)sc < q) sc = nextafterf(sc, INFINITY);
     with_periodic(P, [&](auto per) {
         constexpr int kPer = decltype(per)::value;
         if (full)
             k_candidates_full<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
-                                                                    W.nk, W.cand, kap, k2f);
+                                                                    W.nk, W.cand, kap, sc);
         else
             k_candidates<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
-                                                               W.nk, W.cand, kap, k2f);
+                                                               W.nk, W.cand, kap, sc);
     });
 }
 
