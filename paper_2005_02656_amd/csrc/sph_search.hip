@@ -364,6 +364,9 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
             return g2 < hc * hc;
         },
         [&](int32_t b, const Pos4f& q) {
+            // r^2 may fuse multiply-adds: the widening factor of the reach
+            // covers its FP32 rounding either way
+#pragma clang fp contract(fast)
             // minimum image without branches: the shift is 0 on open axes
             float d[3] = {q.x - fa.x, q.y - fa.y, q.z - fa.z};
 #pragma unroll
