@@ -270,8 +270,12 @@ sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** n
                               const int32_t** ns, const int32_t** list, int32_t* capacity);
 
 /* (host) Device pointers into ws after sph_step with h_ratio_max <= 1.25 (the
- * fused path): nk (int32[n]), each slot's true candidate count (pairs within
- * 2*h_ratio_max*max(h0_a, h0_b)), and the candidate capacity per slot. */
+ * fused path): nk (int32[n]), each slot's candidate count, and the candidate
+ * capacity per slot.  The candidates of a slot are every b != a within
+ * 2*lambda*max(h0_a, h0_b) (lambda = min(1.05, h_ratio_max), or h_ratio_max
+ * when the full-reach pass ran), plus any pairs the FP32 prefilter's rounding
+ * margin admits beyond that reach (within a relative 2^-20 of the box extent
+ * and 2^-18 of the squared reach). */
 sph_status sph_candidates_view(const sph_config* cfg, void* ws, const int32_t** nk,
                                int32_t* capacity);
 
