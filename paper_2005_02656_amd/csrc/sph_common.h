@@ -267,6 +267,41 @@ SPH_DEV double disp_p(const Params& P, double xa, double ya, double za, double x
     return r2;
 }
 
+// The two lanes of a pair (2q, 2q+1) swap a 32-bit value (quad permute 1 0 3 2).
+SPH_DEV int32_t pair_swap(int32_t v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+}
+SPH_DEV double pair_swap(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)pair_swap((int32_t)(uint32_t)u);
+    const uint32_t hi = (uint32_t)pair_swap((int32_t)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Record b (four doubles, 32 bytes) of this lane, gathered by the two lanes of
+// a pair together: one 16-byte load per lane fetches the even lane's record
+// (first half to the even lane, second to the odd one) and a second the odd
+// lane's, so each load touches one line per pair instead of one per lane; a
+// swap then completes each lane's own record.  Both lanes must be active.
+template <class T>
+SPH_DEV T pair_gather32(const T* __restrict__ base, int32_t b, int odd)
+{
+    static_assert(sizeof(T) == 32, "a record of four doubles");
+    const int32_t o = pair_swap(b);
+    const int32_t rA = odd ? o : b;   // the even lane's record
+    const int32_t rB = odd ? b : o;   // the odd lane's record
+    const double2* half = (const double2*)base;
+    const double2 A = half[2 * (int64_t)rA + odd];
+    const double2 B = half[2 * (int64_t)rB + odd];
+    // even lane: A = first half of its own record, B = first half of the odd
+    // lane's; odd lane: A = second half of the even lane's, B = its own
+    const double r0 = pair_swap(odd ? A.x : B.x);
+    const double r1 = pair_swap(odd ? A.y : B.y);
+    return odd ? T{r0, r1, B.x, B.y} : T{A.x, A.y, r0, r1};
+}
+
 // calls f(std::integral_constant<int, kPer>) for the periodic axes of P
 template <class F>
 inline void with_periodic(const Params& P, F&& f)

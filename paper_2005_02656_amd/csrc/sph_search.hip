@@ -463,19 +463,6 @@ __device__ __forceinline__ void load_chunk_or_self(const int32_t* __restrict__ c
 }
 
 // Newton iterations summing over the candidate list (self term added: S(0) = 1)
-// The two lanes of a pair (2q, 2q+1) swap a 32-bit value (quad permute 1 0 3 2).
-__device__ __forceinline__ int32_t pair_swap(int32_t v)
-{
-    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
-}
-__device__ __forceinline__ double pair_swap(double v)
-{
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)pair_swap((int32_t)(uint32_t)u);
-    const uint32_t hi = (uint32_t)pair_swap((int32_t)(uint32_t)(u >> 32));
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
 // x, y, z of candidate b of this lane, gathered by the two lanes of a pair
 // together: one 16-byte load per lane fetches the even lane's record (x, y to
 // the even lane, z, h to the odd one) and a second the odd lane's, so the two
@@ -497,22 +484,6 @@ __device__ __forceinline__ void pair_gather_xyz(const Pos4* __restrict__ p4, int
     x = odd ? r0 : A.x;
     y = odd ? r1 : A.y;
     z = odd ? B.x : r0;
-}
-
-// the whole record {x, y, z, h} of candidate b, gathered as above
-__device__ __forceinline__ Pos4 pair_gather_pos4(const Pos4* __restrict__ p4, int32_t b, int odd)
-{
-    const int32_t o = pair_swap(b);
-    const int32_t rA = odd ? o : b;
-    const int32_t rB = odd ? b : o;
-    const double2* half = (const double2*)p4;
-    const double2 A = half[2 * (int64_t)rA + odd];
-    const double2 B = half[2 * (int64_t)rB + odd];
-    // even lane: A = (x, y) own, B = (x, y) of the odd lane's record;
-    // odd lane: A = (z, h) of the even lane's record, B = (z, h) own
-    const double r0 = pair_swap(odd ? A.x : B.x);
-    const double r1 = pair_swap(odd ? A.y : B.y);
-    return odd ? Pos4{r0, r1, B.x, B.y} : Pos4{A.x, A.y, r0, r1};
 }
 
 template <int kPer>
@@ -639,7 +610,7 @@ __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Dom
         double mb[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            q[u] = pair_gather_pos4(p4, bb[u], odd);
+            q[u] = pair_gather32(p4, bb[u], odd);
             if (kDens) mb[u] = O.m[bb[u]];
         }
 #pragma unroll
