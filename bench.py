@@ -84,7 +84,8 @@ def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True):
         # the target, {x y z m/rho} records, count and list, the record's other
         # sources (m rho omega p c v), C and the 144-byte records out
         "iad": (16 + 32 + 8 + 32) + 32 + 32 + 4 + 4 * k_g + 64 + 48 + 144,
-        "momentum_energy": 144 + 8 + 8 + 4 * k_s + 32,  # record, u, counts, list, out
+        # the target's record, its C rho omega p, u, counts, list, 4 out
+        "momentum_energy": 144 + 48 + 24 + 8 + 8 + 4 * k_s + 32,
         "integrate": 13 * 8 + 4 * 8 + 11 * 8,          # state + rates in, state out
     }[phase]
 

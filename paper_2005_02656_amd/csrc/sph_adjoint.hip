@@ -652,6 +652,8 @@ hipError_t launch_step_backward(const Params& P, const Ws& W, const sph_particle
     GradOut gi{gin->x, gin->y, gin->z, gin->vx, gin->vy, gin->vz, gin->vhx, gin->vhy, gin->vhz,
                gin->u, gin->du_m1};
     MomFwd F{W.p4, W.rec, p->rho, p->omega, p->c, p->u, W.vol};
+    hipError_t e = launch_pack_rec(P, W, p, s);
+    if (e != hipSuccess) return e;
     k_adj_integrate<<<nb, kBlock, 0, s>>>(P, g, go, J);
     k_adj_momentum<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.nc, W.ns, W.list, F, J);
     k_adj_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.nc, W.ns, W.list, W.p4, p->m, p->rho, p->omega,

@@ -87,14 +87,35 @@ constexpr float kWalkGrow = 1.0f + 0x1p-18f;
 struct alignas(32) PosV {
     double x, y, z, v;
 };
-// everything the momentum/energy pass needs of a neighbour (144 B: nine
-// 16-byte loads; the gathers of this pass cost in proportion to their bytes)
+// everything the momentum/energy pass needs of a neighbour.  With d = x_b - x_a
+// the b-side terms of a_a are
+//   m_b P_b/(Omega_b rho_b^2) C_b d W_b = q_b W_b K_b d   (pressure)
+//   (m_b/rho_b) C_b d W_b               = W_b K_b d       (viscosity),
+// so C_b, 1/rho_b, P_b/(Omega_b rho_b^2) and m_b fold into K_b = (m_b/rho_b) C_b
+// and q_b = P_b/(Omega_b rho_b); m_b stays for the a-side terms.
+// A neighbour's fields fill the first eight 16-byte columns; the ninth holds h,
+// which only the target reads.  The stride of nine columns, an odd number,
+// matters: the lanes of a wavefront load the same field of different records,
+// and an odd stride puts those fields in different columns of their cache
+// lines.  (At 64 M particles the pass took 63 ms so, 82 ms with 128-byte
+// records, where they all share one column, and 70 ms with a neighbour field
+// in the ninth column, one more load per neighbour.)
+struct alignas(16) MomNbr {
+    double x, y, z, ih;                    // position and 1/h
+    double k11, k12, k13, k22, k23, k33;   // K = (m/rho) C, C = tau^-1
+    double q, c, m;                        // P/(Omega rho), sound speed, mass
+    double vx, vy, vz;
+    double h, spare;                       // smoothing length (the target's own)
+};
+static_assert(sizeof(MomNbr) == 144, "an odd number of 16-byte columns");
+// the reverse pass reads the factors unfolded (144 B)
 struct alignas(16) MomRec {
     double x, y, z, h;                     // position and smoothing length
     double c11, c12, c13, c22, c23, c33;   // IAD matrix C = tau^-1
     double irho, c, pb, m;                 // 1/rho, sound speed, P/(Omega rho^2), mass
     double vx, vy, vz, invh;
 };
+static_assert(sizeof(MomNbr) <= sizeof(MomRec), "MomNbr records alias the MomRec area");
 struct alignas(16) CellRange {
     int32_t s, e;   // particle slots [s, e) of one Morton cell
     double hmax;    // largest h in the cell (set before the symmetric searches)
@@ -170,7 +191,7 @@ struct Ws {
     int32_t *nc, *ns, *list;
     int32_t *nk, *cand;        // candidate counts and lists of the fused step
     Pos4* p4;
-    MomRec* rec;
+    MomRec* rec;               // the reverse pass's records; the step's MomNbr alias them
     double* vol;               // m/rho per particle (IAD pass)
     PosV* pv;                  // position and m/rho (IAD neighbour records)
     Pos4f* pf;                 // FP32 walk records of the fused candidate pass
@@ -519,6 +540,8 @@ hipError_t launch_density(const Params& P, const Layout& L, const Ws& W, sph_par
 // write_rec: also fill the momentum records (sph_step), else momentum packs them
 hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
                       hipStream_t s, bool pack, bool write_rec);
+// the unfolded 144-byte records the reverse pass reads (over the step's MomNbr)
+hipError_t launch_pack_rec(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s);
 hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
                                   sph_particles* p, hipStream_t s, bool pack);
 // mixed-precision forms of the three pair passes (precision SPH_MIXED)

@@ -11,7 +11,8 @@
 // 3x3 inversion, the integrator and the global sums stay in FP64.
 //
 // Gathered bytes per neighbour: 16 (position) + 4 (mass or volume) in the
-// density and IAD passes, 16 + 64 in the momentum pass (FP64: 32 + 8, 32 + 128).
+// density and IAD passes, one 80-byte record in the momentum pass (FP64: 32 +
+// 8, 32 and 144).
 #include "sph_common.h"
 
 namespace sph {
@@ -22,11 +23,17 @@ struct alignas(16) PosM {
     float ox, oy, oz;     // offset from the cell origin
     uint32_t cpack;       // cell coordinates, 10 bits per axis (x | y << 10 | z << 20)
 };
+// a neighbour's momentum/energy record: its position as in PosM, then the
+// folded factors of the FP64 record (K = (m/rho) C, q = P/(Omega rho)).  Five
+// 16-byte columns: an odd stride puts the same field of the records that the
+// lanes of a wavefront load in different columns of their cache lines.
 struct alignas(16) RecM {
-    float c11, c12, c13, c22, c23, c33;
-    float irho, c, pb, m;
-    float vx, vy, vz, invh;
-    float pad0, pad1;
+    float ox, oy, oz;
+    uint32_t cpack;
+    float k11, k12, k13, k22, k23, k33;
+    float q, c, m, ih;
+    float vx, vy, vz;
+    float spare[3];
 };
 
 struct CellGeom {
@@ -201,20 +208,22 @@ struct RecSrcM {
     const double *m, *rho, *omega, *p, *c, *vx, *vy, *vz, *h;
 };
 
-__device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, double c11, double c12,
-                                          double c13, double c22, double c23, double c33)
+__device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, const PosM& pa,
+                                          double c11, double c12, double c13, double c22,
+                                          double c23, double c33)
 {
     RecM q;
-    q.c11 = (float)c11; q.c12 = (float)c12; q.c13 = (float)c13;
-    q.c22 = (float)c22; q.c23 = (float)c23; q.c33 = (float)c33;
-    const double r = R.rho[a];
-    q.irho = (float)(1.0 / r);
+    q.ox = pa.ox; q.oy = pa.oy; q.oz = pa.oz; q.cpack = pa.cpack;
+    const double r = R.rho[a], m = R.m[a];
+    const double v = m / r;
+    q.k11 = (float)(v * c11); q.k12 = (float)(v * c12); q.k13 = (float)(v * c13);
+    q.k22 = (float)(v * c22); q.k23 = (float)(v * c23); q.k33 = (float)(v * c33);
+    q.q = (float)(R.p[a] / (R.omega[a] * r));
     q.c = (float)R.c[a];
-    q.pb = (float)(R.p[a] / (R.omega[a] * r * r));
-    q.m = (float)R.m[a];
+    q.m = (float)m;
+    q.ih = (float)(1.0 / R.h[a]);
     q.vx = (float)R.vx[a]; q.vy = (float)R.vy[a]; q.vz = (float)R.vz[a];
-    q.invh = (float)(1.0 / R.h[a]);
-    q.pad0 = 0.0f; q.pad1 = 0.0f;
+    q.spare[0] = q.spare[1] = q.spare[2] = 0.0f;
     return q;
 }
 
@@ -294,10 +303,11 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
     }
     c11[a] = a11; c12[a] = a12; c13[a] = a13;
     c22[a] = a22; c23[a] = a23; c33[a] = a33;
-    if (rec) rec[a] = make_recm(R, a, a11, a12, a13, a22, a23, a33);
+    if (rec) rec[a] = make_recm(R, a, pa, a11, a12, a13, a22, a23, a33);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_recm(int64_t n, RecSrcM R,
+                                                      const PosM* __restrict__ pm,
                                                       const double* __restrict__ c11,
                                                       const double* __restrict__ c12,
                                                       const double* __restrict__ c13,
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_recm(int64_t n, RecSrcM R,
                                                       RecM* __restrict__ rec)
 {
     int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (a < n) rec[a] = make_recm(R, a, c11[a], c12[a], c13[a], c22[a], c23[a], c33[a]);
+    if (a < n) rec[a] = make_recm(R, a, pm[a], c11[a], c12[a], c13[a], c22[a], c23[a], c33[a]);
 }
 
 struct MomOutM {
@@ -316,14 +326,19 @@ struct MomOutM {
 
 __global__ void k_dtmin_begin_m(Domain* d) { d->dtmin_bits = ord_bits(INFINITY); }
 
+// what the target reads of itself beside its record (FP64 arrays)
+struct MomSelfM {
+    const double *h, *c, *c11, *c12, *c13, *c22, *c23, *c33, *rho, *omega, *p;
+};
+
+__device__ __forceinline__ PosM rec_pos(const RecM& r) { return PosM{r.ox, r.oy, r.oz, r.cpack}; }
+
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momentum_energy_m(Params P, Domain* __restrict__ dom,
                                                               const int32_t* __restrict__ nc,
                                                               const int32_t* __restrict__ ns,
                                                               const int32_t* __restrict__ list,
-                                                              const PosM* __restrict__ pm,
                                                               const RecM* __restrict__ rec,
-                                                              const double* __restrict__ h,
-                                                              const double* __restrict__ cdbl,
+                                                              MomSelfM T,
                                                               const double* __restrict__ u,
                                                               MomOutM O)
 {
@@ -334,14 +349,18 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
     double dtc = INFINITY;
     if (a < P.n) {
         const CellGeom g = cell_geom(P, *dom);
-        const PosM pa = pm[a];
         const RecM ra = rec[a];
-        const double ha = h[a];
+        const PosM pa = rec_pos(ra);
+        const double ha = T.h[a];
         const float tsa = (float)(kPiHalfSq / (ha * ha));
         const float w0a = (float)(P.bn / (ha * ha * ha));
         const float bn = (float)P.bn;
         const float al = (float)P.alpha;
-        const float pa_ = ra.pb, ira = ra.irho, ca = ra.c;
+        const double rho_a = T.rho[a];
+        const float pa_ = (float)(T.p[a] / (T.omega[a] * rho_a * rho_a));   // P/(Omega rho^2)
+        const float ira = (float)(1.0 / rho_a), ca = ra.c;
+        const float ca11 = (float)T.c11[a], ca12 = (float)T.c12[a], ca13 = (float)T.c13[a];
+        const float ca22 = (float)T.c22[a], ca23 = (float)T.c23[a], ca33 = (float)T.c33[a];
         const int ng = P.ng_max;
         const int cg = min(nc[a], ng);
         const int co = min(ns[a] - nc[a], ng);
@@ -363,13 +382,10 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
         for (int k0 = 0; k0 < total; k0 += kB) {
             bool okv[kB];
             RecM rbv[kB];
-            PosM qv[kB];
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
                 okv[u] = (uint32_t)nx[u] < (uint32_t)P.n;
-                const int32_t b = okv[u] ? nx[u] : (int32_t)a;
-                rbv[u] = rec[b];
-                qv[u] = pm[b];
+                rbv[u] = rec[okv[u] ? nx[u] : (int32_t)a];
             }
             entries(k0 + kB, nx);
 #pragma unroll
@@ -379,38 +395,38 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
             const bool gather = k0 + u < cg;
             const RecM& rb = rbv[u];
             float dx, dy, dz;
-            const float r2 = disp_m(g, pa, qv[u], dx, dy, dz);
+            const float r2 = disp_m(g, pa, rec_pos(rb), dx, dy, dz);
             float Wa = 0.0f;
             if (gather) Wa = w0a * sinc_S_f(r2 * tsa, P.sinc_n);
             // support of W(h_b): v_b < 2, i.e. t_b < pi^2
-            const float ih2 = rb.invh * rb.invh;
+            const float ih2 = rb.ih * rb.ih;
             const float tb = r2 * ((float)kPiHalfSq * ih2);
             float Wb = 0.0f;
-            if (tb < (float)(4.0 * kPiHalfSq)) Wb = bn * (ih2 * rb.invh) * sinc_S_f(tb, P.sinc_n);
-            const float Aax = (ra.c11 * dx + ra.c12 * dy + ra.c13 * dz) * Wa;
-            const float Aay = (ra.c12 * dx + ra.c22 * dy + ra.c23 * dz) * Wa;
-            const float Aaz = (ra.c13 * dx + ra.c23 * dy + ra.c33 * dz) * Wa;
-            const float Abx = (rb.c11 * dx + rb.c12 * dy + rb.c13 * dz) * Wb;
-            const float Aby = (rb.c12 * dx + rb.c22 * dy + rb.c23 * dz) * Wb;
-            const float Abz = (rb.c13 * dx + rb.c23 * dy + rb.c33 * dz) * Wb;
+            if (tb < (float)(4.0 * kPiHalfSq)) Wb = bn * (ih2 * rb.ih) * sinc_S_f(tb, P.sinc_n);
+            const float Aax = (ca11 * dx + ca12 * dy + ca13 * dz) * Wa;
+            const float Aay = (ca12 * dx + ca22 * dy + ca23 * dz) * Wa;
+            const float Aaz = (ca13 * dx + ca23 * dy + ca33 * dz) * Wa;
+            const float Kx = rb.k11 * dx + rb.k12 * dy + rb.k13 * dz;
+            const float Ky = rb.k12 * dx + rb.k22 * dy + rb.k23 * dz;
+            const float Kz = rb.k13 * dx + rb.k23 * dy + rb.k33 * dz;
             const float vx = ra.vx - rb.vx, vy = ra.vy - rb.vy, vz = ra.vz - rb.vz;
             const float xv = -(vx * dx + vy * dy + vz * dz);
-            float Pi = 0.0f;
+            float hPi = 0.0f;   // Pi_ab / 2
             if (xv < 0.0f) {
                 const float w = xv * rsqrtf(r2);
                 const float vsig = ca + rb.c - 3.0f * w;
-                Pi = -0.5f * al * vsig * w;
+                hPi = -0.25f * al * vsig * w;
             }
             const float mb = rb.m;
-            const float gk = 0.5f * mb * Pi;
-            const float gx = gk * (Aax * ira + Abx * rb.irho);
-            const float gy = gk * (Aay * ira + Aby * rb.irho);
-            const float gz = gk * (Aaz * ira + Abz * rb.irho);
-            axs += (double)(-(mb * (pa_ * Aax + rb.pb * Abx)) - gx);
-            ays += (double)(-(mb * (pa_ * Aay + rb.pb * Aby)) - gy);
-            azs += (double)(-(mb * (pa_ * Aaz + rb.pb * Abz)) - gz);
-            e1 += (double)(mb * (vx * Aax + vy * Aay + vz * Aaz));
-            e2 += (double)(vx * gx + vy * gy + vz * gz);
+            const float sa = mb * (pa_ + hPi * ira);
+            const float sb = (rb.q + hPi) * Wb;
+            axs += (double)(-(sa * Aax + sb * Kx));
+            ays += (double)(-(sa * Aay + sb * Ky));
+            azs += (double)(-(sa * Aaz + sb * Kz));
+            const float va = vx * Aax + vy * Aay + vz * Aaz;
+            const float vk = vx * Kx + vy * Ky + vz * Kz;
+            e1 += (double)(mb * va);
+            e2 += (double)(hPi * (mb * ira * va + Wb * vk));
             }
         }
         // the energy rate is assembled in FP64
@@ -421,7 +437,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
         O.du[a] = du;
         if (!isfinite(axs) || !isfinite(ays) || !isfinite(azs) || !isfinite(du))
             set_err(dom, SPH_ERRBIT_NONFINITE);
-        const double cA = cdbl[a];
+        const double cA = T.c[a];
         dtc = P.courant * (ha / cA);
         if (P.acc_dt > 0.0) {
             double am = sqrt((axs * axs + ays * ays) + azs * azs);
@@ -446,7 +462,8 @@ RecSrcM recm_src(const sph_particles* p)
 }  // namespace
 
 static_assert(sizeof(PosM) == 16, "PosM layout");
-static_assert(sizeof(RecM) == 64, "RecM layout");
+static_assert(sizeof(RecM) == 80, "RecM layout");
+static_assert(sizeof(RecM) <= sizeof(MomRec), "RecM records alias the MomRec area");
 size_t mixed_posm_bytes() { return sizeof(PosM); }
 size_t mixed_rec_bytes() { return sizeof(RecM); }
 
@@ -494,13 +511,14 @@ hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const 
     RecM* rec = (RecM*)W.recm;
     if (pack) {
         k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
-        k_pack_recm<<<nb, kBlock, 0, s>>>(P.n, recm_src(p), p->c11, p->c12, p->c13, p->c22,
-                                          p->c23, p->c33, rec);
+        k_pack_recm<<<nb, kBlock, 0, s>>>(P.n, recm_src(p), pm, p->c11, p->c12, p->c13,
+                                          p->c22, p->c23, p->c33, rec);
     }
     MomOutM O{p->ax, p->ay, p->az, p->du};
+    MomSelfM T{p->h, p->c, p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p};
     k_dtmin_begin_m<<<1, 1, 0, s>>>(W.dom);
-    k_momentum_energy_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, pm, rec,
-                                                        p->h, p->c, p->u, O);
+    k_momentum_energy_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, rec, T,
+                                                        p->u, O);
     return hipGetLastError();
 }
 

@@ -92,20 +92,22 @@ struct RecSrc {
     const double *m, *rho, *omega, *p, *c, *vx, *vy, *vz, *h, *x, *y, *z;
 };
 
-__device__ __forceinline__ MomRec make_rec(const RecSrc& R, int64_t a, const Pos4& pa,
+__device__ __forceinline__ MomNbr make_nbr(const RecSrc& R, int64_t a, const Pos4& pa,
                                            double c11, double c12, double c13, double c22,
                                            double c23, double c33)
 {
-    MomRec q;
+    MomNbr q;
     q.x = pa.x; q.y = pa.y; q.z = pa.z; q.h = pa.h;
-    q.c11 = c11; q.c12 = c12; q.c13 = c13; q.c22 = c22; q.c23 = c23; q.c33 = c33;
-    const double r = R.rho[a];
-    q.irho = 1.0 / r;
+    q.ih = 1.0 / pa.h;
+    const double r = R.rho[a], m = R.m[a];
+    const double v = m / r;
+    q.k11 = v * c11; q.k12 = v * c12; q.k13 = v * c13;
+    q.k22 = v * c22; q.k23 = v * c23; q.k33 = v * c33;
+    q.q = R.p[a] / (R.omega[a] * r);
     q.c = R.c[a];
-    q.pb = R.p[a] / (R.omega[a] * r * r);
-    q.m = R.m[a];
+    q.m = m;
     q.vx = R.vx[a]; q.vy = R.vy[a]; q.vz = R.vz[a];
-    q.invh = 1.0 / pa.h;
+    q.spare = 0.0;
     return q;
 }
 
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
                                                 double* __restrict__ c11, double* __restrict__ c12,
                                                 double* __restrict__ c13, double* __restrict__ c22,
                                                 double* __restrict__ c23, double* __restrict__ c33,
-                                                RecSrc R, MomRec* __restrict__ rec)
+                                                RecSrc R, MomNbr* __restrict__ rec)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
@@ -180,10 +182,27 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
     }
     c11[a] = a11; c12[a] = a12; c13[a] = a13;
     c22[a] = a22; c23[a] = a23; c33[a] = a33;
-    if (rec) rec[a] = make_rec(R, a, pa, a11, a12, a13, a22, a23, a33);
+    if (rec) rec[a] = make_nbr(R, a, pa, a11, a12, a13, a22, a23, a33);
 }
 
+__global__ __launch_bounds__(kBlock) void k_pack_nbr(int64_t n, RecSrc R,
+                                                     const double* __restrict__ c11,
+                                                     const double* __restrict__ c12,
+                                                     const double* __restrict__ c13,
+                                                     const double* __restrict__ c22,
+                                                     const double* __restrict__ c23,
+                                                     const double* __restrict__ c33,
+                                                     MomNbr* __restrict__ rec)
+{
+    int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (a < n)
+        rec[a] = make_nbr(R, a, Pos4{R.x[a], R.y[a], R.z[a], R.h[a]}, c11[a], c12[a], c13[a],
+                          c22[a], c23[a], c33[a]);
+}
+
+// the reverse pass's unfolded records, from the positions the IAD pass read
 __global__ __launch_bounds__(kBlock) void k_pack_rec(int64_t n, RecSrc R,
+                                                     const Pos4* __restrict__ p4,
                                                      const double* __restrict__ c11,
                                                      const double* __restrict__ c12,
                                                      const double* __restrict__ c13,
@@ -192,10 +211,21 @@ __global__ __launch_bounds__(kBlock) void k_pack_rec(int64_t n, RecSrc R,
                                                      const double* __restrict__ c33,
                                                      MomRec* __restrict__ rec)
 {
-    int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (a < n)
-        rec[a] = make_rec(R, a, Pos4{R.x[a], R.y[a], R.z[a], R.h[a]}, c11[a], c12[a], c13[a],
-                          c22[a], c23[a], c33[a]);
+    const int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (a >= n) return;
+    const Pos4 pa = p4[a];
+    MomRec q;
+    q.x = pa.x; q.y = pa.y; q.z = pa.z; q.h = pa.h;
+    q.c11 = c11[a]; q.c12 = c12[a]; q.c13 = c13[a];
+    q.c22 = c22[a]; q.c23 = c23[a]; q.c33 = c33[a];
+    const double r = R.rho[a];
+    q.irho = 1.0 / r;
+    q.c = R.c[a];
+    q.pb = R.p[a] / (R.omega[a] * r * r);
+    q.m = R.m[a];
+    q.vx = R.vx[a]; q.vy = R.vy[a]; q.vz = R.vz[a];
+    q.invh = 1.0 / pa.h;
+    rec[a] = q;
 }
 
 struct MomOut {
@@ -204,11 +234,17 @@ struct MomOut {
 
 __global__ void k_dtmin_begin(Domain* d) { d->dtmin_bits = ord_bits(INFINITY); }
 
+// what the target reads of itself beside its record: the unfolded factors
+struct MomSelf {
+    const double *c11, *c12, *c13, *c22, *c23, *c33, *rho, *omega, *p;
+};
+
 __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
                                                             const int32_t* __restrict__ list,
-                                                            const MomRec* __restrict__ rec,
+                                                            const MomNbr* __restrict__ rec,
+                                                            MomSelf T,
                                                             const double* __restrict__ u,
                                                             MomOut O)
 {
@@ -218,10 +254,14 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
     const int64_t a = lb * kBlock + threadIdx.x;
     double dtc = INFINITY;
     if (a < P.n) {
-        const MomRec ra = rec[a];
+        const MomNbr ra = rec[a];
         const double xa = ra.x, ya = ra.y, za = ra.z, ha = ra.h;
         const double vxa = ra.vx, vya = ra.vy, vza = ra.vz;
-        const double ca = ra.c, ira = ra.irho, pa_ = ra.pb;
+        const double ca11 = T.c11[a], ca12 = T.c12[a], ca13 = T.c13[a];
+        const double ca22 = T.c22[a], ca23 = T.c23[a], ca33 = T.c33[a];
+        const double rho_a = T.rho[a];
+        const double ca = ra.c, ira = 1.0 / rho_a;
+        const double pa_ = T.p[a] / (T.omega[a] * rho_a * rho_a);   // P/(Omega rho^2)
         const double tsa = kPiHalfSq / (ha * ha);
         const double w0a = P.bn / (ha * ha * ha);
         const double al = P.alpha;
@@ -240,7 +280,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
                 e[u] = (k < total) ? list[lpos(a, j, ng)] : -1;
             }
         };
-        auto pair = [&](bool gather, const MomRec& rb) {
+        auto pair = [&](bool gather, const MomNbr& rb) {
 #if SPH_PAIR_CONTRACT
             // the pair terms may fuse multiply-adds (rounding-level changes
             // only); r^2 itself comes from disp(), which never contracts
@@ -250,38 +290,39 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             double r2 = disp(P, xa, ya, za, rb.x, rb.y, rb.z, dx, dy, dz);
             double Wa = 0.0;
             if (gather) Wa = w0a * sinc_S(r2 * tsa, P.sinc_n);
+            // W(r, h_b) on its support t_b < pi^2 (v_b < 2)
             double Wb = 0.0;
-            const double hb2 = 2.0 * rb.h;
-            if (r2 < hb2 * hb2) {
-                const double ih = rb.invh, ih2 = ih * ih;
-                Wb = P.bn * (ih2 * ih) * sinc_S(r2 * (kPiHalfSq * ih2), P.sinc_n);
-            }
-            // A_ab(h_a) = C_a d W_a, A_ab(h_b) = C_b d W_b, d = x_b - x_a
-            const double Aax = (ra.c11 * dx + ra.c12 * dy + ra.c13 * dz) * Wa;
-            const double Aay = (ra.c12 * dx + ra.c22 * dy + ra.c23 * dz) * Wa;
-            const double Aaz = (ra.c13 * dx + ra.c23 * dy + ra.c33 * dz) * Wa;
-            const double Abx = (rb.c11 * dx + rb.c12 * dy + rb.c13 * dz) * Wb;
-            const double Aby = (rb.c12 * dx + rb.c22 * dy + rb.c23 * dz) * Wb;
-            const double Abz = (rb.c13 * dx + rb.c23 * dy + rb.c33 * dz) * Wb;
+            const double ih = rb.ih, ih2 = ih * ih;
+            const double tb = r2 * (kPiHalfSq * ih2);
+            if (tb < 4.0 * kPiHalfSq) Wb = P.bn * (ih2 * ih) * sinc_S(tb, P.sinc_n);
+            // A_ab(h_a) = C_a d W_a and K_b d with d = x_b - x_a
+            const double Aax = (ca11 * dx + ca12 * dy + ca13 * dz) * Wa;
+            const double Aay = (ca12 * dx + ca22 * dy + ca23 * dz) * Wa;
+            const double Aaz = (ca13 * dx + ca23 * dy + ca33 * dz) * Wa;
+            const double Kx = rb.k11 * dx + rb.k12 * dy + rb.k13 * dz;
+            const double Ky = rb.k12 * dx + rb.k22 * dy + rb.k23 * dz;
+            const double Kz = rb.k13 * dx + rb.k23 * dy + rb.k33 * dz;
             const double vx = vxa - rb.vx, vy = vya - rb.vy, vz = vza - rb.vz;
             // x_ab . v_ab with x_ab = -d
             const double xv = -(vx * dx + vy * dy + vz * dz);
-            double Pi = 0.0;
+            double hPi = 0.0;   // Pi_ab / 2
             if (xv < 0.0) {
                 const double w = xv * rsqrt_nr(r2);
                 const double vsig = ca + rb.c - 3.0 * w;
-                Pi = -0.5 * al * vsig * w;
+                hPi = -0.25 * al * vsig * w;
             }
+            // a_a -= m_b (pb_a + Pi/(2 rho_a)) A_ab(h_a) + (q_b + Pi/2) W_b K_b d
             const double mb = rb.m;
-            const double gk = 0.5 * mb * Pi;
-            const double gx = gk * (Aax * ira + Abx * rb.irho);
-            const double gy = gk * (Aay * ira + Aby * rb.irho);
-            const double gz = gk * (Aaz * ira + Abz * rb.irho);
-            axs += -(mb * (pa_ * Aax + rb.pb * Abx)) - gx;
-            ays += -(mb * (pa_ * Aay + rb.pb * Aby)) - gy;
-            azs += -(mb * (pa_ * Aaz + rb.pb * Abz)) - gz;
-            e1 += mb * (vx * Aax + vy * Aay + vz * Aaz);
-            e2 += vx * gx + vy * gy + vz * gz;
+            const double sa = mb * (pa_ + hPi * ira);
+            const double sb = (rb.q + hPi) * Wb;
+            axs -= sa * Aax + sb * Kx;
+            ays -= sa * Aay + sb * Ky;
+            azs -= sa * Aaz + sb * Kz;
+            // e1 += m_b v_ab . A_ab(h_a); e2 += v_ab . (Pi/2)(m_b A_ab(h_a)/rho_a + W_b K_b d)
+            const double va = vx * Aax + vy * Aay + vz * Aaz;
+            const double vk = vx * Kx + vy * Ky + vz * Kz;
+            e1 += mb * va;
+            e2 += hPi * (mb * ira * va + Wb * vk);
         };
         // the records of a batch are gathered, then the next batch's list
         // entries fetched while this batch computes (entries past the end read
@@ -290,7 +331,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
         entries(0, nx);
         for (int k0 = 0; k0 < total; k0 += kMomBatch) {
             bool ok[kMomBatch];
-            MomRec rb[kMomBatch];
+            MomNbr rb[kMomBatch];
 #pragma unroll
             for (int u = 0; u < kMomBatch; ++u) {
                 ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
@@ -369,7 +410,15 @@ hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particl
     k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.p4, W.vol, W.pv);
     k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12,
                                           p->c13, p->c22, p->c23, p->c33, rec_src(p),
-                                          write_rec ? W.rec : nullptr);
+                                          write_rec ? (MomNbr*)W.rec : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_rec(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    k_pack_rec<<<nb, kBlock, 0, s>>>(P.n, rec_src(p), W.p4, p->c11, p->c12, p->c13, p->c22,
+                                     p->c23, p->c33, W.rec);
     return hipGetLastError();
 }
 
@@ -380,13 +429,14 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
     if (pack) {
         hipError_t e = launch_pack_p4(P, W, p, s);
         if (e != hipSuccess) return e;
-        k_pack_rec<<<nb, kBlock, 0, s>>>(P.n, rec_src(p), p->c11, p->c12, p->c13, p->c22,
-                                         p->c23, p->c33, W.rec);
+        k_pack_nbr<<<nb, kBlock, 0, s>>>(P.n, rec_src(p), p->c11, p->c12, p->c13, p->c22,
+                                         p->c23, p->c33, (MomNbr*)W.rec);
     }
     MomOut O{p->ax, p->ay, p->az, p->du};
+    MomSelf T{p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p};
     k_dtmin_begin<<<1, 1, 0, s>>>(W.dom);
-    k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, W.rec, p->u,
-                                                      O);
+    k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list,
+                                                      (const MomNbr*)W.rec, T, p->u, O);
     return hipGetLastError();
 }
 
