@@ -451,7 +451,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
     }
     for (int o = 32; o > 0; o >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, o, 64));
     if ((threadIdx.x & 63) == 0 && dtc < INFINITY)
-        atomicMin((unsigned long long*)&dom->dtmin_bits, (unsigned long long)ord_bits(dtc));
+        ord_min_to(&dom->dtmin_bits, dtc);
 }
 
 RecSrcM recm_src(const sph_particles* p)

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
     // block minimum of the candidates, one atomic per wavefront
     for (int o = 32; o > 0; o >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, o, 64));
     if ((threadIdx.x & 63) == 0 && dtc < INFINITY)
-        atomicMin((unsigned long long*)&dom->dtmin_bits, (unsigned long long)ord_bits(dtc));
+        ord_min_to(&dom->dtmin_bits, dtc);
 }
 
 __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals* g)

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_cells_hmax(Params P, Domain* __restr
     }
     for (int o = 32; o > 0; o >>= 1) hm = fmax(hm, __shfl_xor(hm, o, 64));
     if ((threadIdx.x & 63) == 0) {
-        atomicMax((unsigned long long*)&dom->hmax_new_bits, (unsigned long long)ord_bits(hm));
+        ord_max_to(&dom->hmax_new_bits, hm);
         if (hm > 0.0) check_cell_range(P, dom, hm);
     }
 }
