@@ -269,10 +269,18 @@ sph_status sph_density_backward(const sph_config* cfg, const sph_particles* p, v
 sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,
                               const int32_t** ns, const int32_t** list, int32_t* capacity);
 
+/* Short candidate reach of the fused step (h_ratio_max <= 1.25): the step
+ * collects candidates within 2*lambda*max(h0_a, h0_b), lambda =
+ * min(SPH_SHORT_REACH, h_ratio_max), and repeats the walk and the Newton
+ * iterations at the full reach h_ratio_max only if an iterate h leaves
+ * lambda*h0.  The lists are exact either way; the constant trades the walk's
+ * volume (lambda^3) against how often h grows past it in one step. */
+#define SPH_SHORT_REACH 1.03
+
 /* (host) Device pointers into ws after sph_step with h_ratio_max <= 1.25 (the
  * fused path): nk (int32[n]), each slot's candidate count, and the candidate
  * capacity per slot.  The candidates of a slot are every b != a within
- * 2*lambda*max(h0_a, h0_b) (lambda = min(1.05, h_ratio_max), or h_ratio_max
+ * 2*lambda*max(h0_a, h0_b) (lambda = min(SPH_SHORT_REACH, h_ratio_max), or h_ratio_max
  * when the full-reach pass ran), plus any pairs the FP32 prefilter's rounding
  * margin admits beyond that reach (within a relative 2^-20 of the box extent
  * and 2^-18 of the squared reach). */

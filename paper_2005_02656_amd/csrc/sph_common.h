@@ -148,13 +148,10 @@ __host__ __device__ inline int64_t lpos8(int64_t a, int j, int cap)
 // workspace layout depends on (n, ng_max) only, never on per-call parameters.
 constexpr double kFusedKappaMax = 1.25;
 // The fused step first collects candidates within 2 lambda max(h0_a, h0_b),
-// lambda = kFusedReach (1.16x the list volume instead of kappa^3 = 1.95x), and
+// lambda = kFusedReach (1.09x the list volume instead of kappa^3 = 1.95x), and
 // runs Newton on them; if any iterate h leaves [0, lambda h0] it repeats both
 // with the full reach kappa.  Either way the sets are exact.
-#ifndef SPH_FUSED_REACH
-#define SPH_FUSED_REACH 1.05
-#endif
-constexpr double kFusedReach = SPH_FUSED_REACH;
+constexpr double kFusedReach = SPH_SHORT_REACH;
 
 // 2 kap in FP32, rounded up (host side)
 inline float reach_f32(double kap)

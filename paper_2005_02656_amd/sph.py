@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_WORKSPACE
                 4: "SPH_E_NEIGHBOR_OVERFLOW", 5: "SPH_E_CELL_RANGE", 6: "SPH_E_NONFINITE",
                 7: "SPH_E_SINGULAR_TAU"}
 ERRBIT_NEIGHBOR_OVERFLOW, ERRBIT_CELL_RANGE, ERRBIT_NONFINITE, ERRBIT_SINGULAR_TAU = 1, 2, 4, 8
+SHORT_REACH = 1.03   # SPH_SHORT_REACH: the fused step's short candidate reach lambda
 FP64, MIXED = 0, 1
 
 STATE_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",

@@ -241,14 +241,14 @@ def test_step_deterministic():
 @pytest.mark.parametrize("name", ["random", "lattice12"])
 def test_fused_step_short_reach(name):
     """The fused step's h and lists are exact whether its short candidate reach
-    holds (lattice: h moves by far less than 5%) or its full-reach pass has to
+    holds (lattice: h moves by far less than 3%) or its full-reach pass has to
     run (random h in [0.06, 0.09]: Newton moves some h by more than 5%)."""
     w = CASES[name]()
     cfg, ocfg = configs(w, ng_max=NG)
     a = w.arrays
     if name == "random":
         h1 = oracle.update_h(ocfg, a["x"], a["y"], a["z"], a["h"])
-        assert np.max(h1 / a["h"]) > 1.05          # the full-reach pass must run
+        assert np.max(h1 / a["h"]) > sph.SHORT_REACH   # the full-reach pass must run
     r = Run(w, cfg)
     sph.step(cfg, r.parts, r.g, r.ws)
     assert r.status() == (0, 0)
@@ -284,7 +284,8 @@ def test_fused_candidates_cover_reach(name):
     """The candidate walk of the fused step tests in FP32 with a widened reach:
     its count for every target lies between the exact number of b != a with
     r_ab < 2 lam max(h0_a, h0_b) and that number at a reach larger by a relative
-    1e-3, for lam the short reach 1.05 or, when the full-reach pass ran, kappa."""
+    1e-3, for lam the short reach (sph.SHORT_REACH) or, when the full-reach pass
+    ran, kappa."""
     w = CASES[name]()
     cfg, _ = configs(w, ng_max=NG)
     r = Run(w, cfg, _with_rho_ref(w))
@@ -294,7 +295,7 @@ def test_fused_candidates_cover_reach(name):
     nk = np.empty(w.n, np.int64)
     nk[r.ids()] = nk_v.cpu().numpy()
     assert nk.max() <= cap
-    lams = sorted({min(1.05, cfg.h_ratio_max), cfg.h_ratio_max})
+    lams = sorted({min(sph.SHORT_REACH, cfg.h_ratio_max), cfg.h_ratio_max})
     fs = [2 * l for l in lams] + [2 * l * (1 + 1e-3) for l in lams]
     cnt = _reach_counts(w, w.arrays["h"], fs)
     ok = [bool(np.all((cnt[2 * l] <= nk) & (nk <= cnt[2 * l * (1 + 1e-3)]))) for l in lams]

@@ -32,6 +32,19 @@ def test_exports_every_declared_symbol(sph):
     assert sorted(sph.EXPORTED) == names
 
 
+def test_constants_match_the_header(sph):
+    src = open(os.path.join(ROOT, "include", "sph.h")).read()
+    defs = dict(re.findall(r"#define (SPH_\w+) (.+)", src))
+    assert float(defs["SPH_SHORT_REACH"]) == sph.SHORT_REACH
+    assert int(defs["SPH_STEP_PHASES"]) == len(sph.STEP_PHASES)
+    shift = lambda d: 1 << int(re.fullmatch(r"\(1u << (\d+)\)", d.strip()).group(1))
+    bits = {k: shift(defs["SPH_ERRBIT_" + k]) for k in
+            ("NEIGHBOR_OVERFLOW", "CELL_RANGE", "NONFINITE", "SINGULAR_TAU")}
+    assert bits == {"NEIGHBOR_OVERFLOW": sph.ERRBIT_NEIGHBOR_OVERFLOW,
+                    "CELL_RANGE": sph.ERRBIT_CELL_RANGE, "NONFINITE": sph.ERRBIT_NONFINITE,
+                    "SINGULAR_TAU": sph.ERRBIT_SINGULAR_TAU}
+
+
 def test_workspace_bytes_validation(sph):
     L = sph.lib()
     good = sph.Config(n=1000)
