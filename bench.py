@@ -62,8 +62,11 @@ FLOPS_PER_PAIR = {
 }
 
 
-def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True):
-    """Algorithmic HBM bytes per particle of one phase of sph_step."""
+def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True, urec=False):
+    """Algorithmic HBM bytes per particle of one phase of sph_step.  urec: the
+    momentum records take m and c from slot 0 (equal masses and sound speeds),
+    112 bytes instead of 144."""
+    rec = 112 if urec else 144
     return {
         # bbox (x y z h), keys, 8 radix passes over 8-byte keys and 4-byte indices,
         # permutation of the state (15 fields with the weakly compressible EOS,
@@ -80,12 +83,13 @@ def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True):
         "lists": 64 + 4 + 4 * k_c + 8 + 4 * k_s + ((64 if wc else 48) if fused else 0),
         # separate density pass (stage path): p4 m u (p_ref rho_ref), list, 4 out
         "density": 0 if fused else (100 if wc else 84) + 4 * k_g,
-        # volume pass: m rho p4 in, m/rho and {x y z m/rho} out; IAD pass: p4 of
-        # the target, {x y z m/rho} records, count and list, the record's other
-        # sources (m rho omega p c v), C and the 144-byte records out
-        "iad": (16 + 32 + 8 + 32) + 32 + 32 + 4 + 4 * k_g + 64 + 48 + 144,
-        # the target's record, its C rho omega p, u, counts, list, 4 out
-        "momentum_energy": 144 + 48 + 24 + 8 + 8 + 4 * k_s + 32,
+        # volume pass: m rho p4 in, m/rho and {x y z m/rho} out; the m and c
+        # uniformity check; IAD pass: p4 of the target, {x y z m/rho} records,
+        # count and list, the record's other sources (m rho omega p c v), C and
+        # the momentum records out
+        "iad": (16 + 32 + 8 + 32) + 16 + 32 + 32 + 4 + 4 * k_g + 64 + 48 + rec,
+        # the target's record, its C rho omega p h, u, counts, list, 4 out
+        "momentum_energy": rec + 48 + 24 + 8 + 8 + 8 + 4 * k_s + 32,
         "integrate": 13 * 8 + 4 * 8 + 11 * 8,          # state + rates in, state out
     }[phase]
 
@@ -133,13 +137,13 @@ def traffic_from_profile(kernel, workload):
         return None
 
 
-def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload, fused):
+def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload, fused, urec=False):
     """Roofline of the phase that takes the longest.  Both ceilings are evaluated
     (algorithmic HBM bytes against 8 TB/s, algorithmic FP64 flops against the
     78.6 TFLOP/s vector peak); the binding one (larger fraction) is reported."""
     dom = max(phases, key=phases.get)
     t = phases[dom] * 1e-3
-    by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters, fused)
+    by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters, fused, urec)
     hbm = by * n / t / 1e9
     kern = PHASE_KERNEL[dom]
     res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom],
@@ -278,6 +282,9 @@ def main():
     k_s = float(ns.double().mean())
     n = cfg.n
     wc = cfg.eos == 1
+    # equal masses under the weakly compressible EOS (c = c0): the momentum
+    # pass reads its 112-byte neighbour records
+    urec = wc and bool(torch.all(parts["m"] == parts["m"][0]))
 
     out = {
         "metric": "particle-updates/s per SPH step at 1 MI355X",
@@ -299,9 +306,9 @@ def main():
         k_c = float(nk.double().mean())
         out["config"]["candidates_mean"] = k_c
     out["roofline"] = roofline(phases, n, k_g, k_s, wc, cfg.newton_iters, k_c, args.workload,
-                               cfg.h_ratio_max <= 1.25)
+                               cfg.h_ratio_max <= 1.25, urec)
     fused = cfg.h_ratio_max <= 1.25
-    step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters, fused)
+    step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters, fused, urec)
                      for k in phases) * n
     out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
     step_flops = n * (FLOPS_PER_PAIR["newton_h"] * cfg.newton_iters * k_c

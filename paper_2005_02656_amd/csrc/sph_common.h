@@ -65,6 +65,7 @@ struct Domain {
     int32_t level, shift, ncell_axis;
     uint32_t err;              // sticky SPH_ERRBIT_* word
     uint32_t refit;            // fused step: an h left the short candidate reach
+    uint32_t nonuniform;       // some m or c differs from slot 0's (full momentum records)
     float walk_slack;          // 2^-20 x the largest extent (FP32 candidate walk)
     int64_t built_n;
 };
@@ -108,6 +109,16 @@ struct alignas(16) MomNbr {
     double h, spare;                       // smoothing length (the target's own)
 };
 static_assert(sizeof(MomNbr) == 144, "an odd number of 16-byte columns");
+// The same record when every particle has the same mass and sound speed (the
+// weakly compressible EOS sets c = c0): m and c come from slot 0, and the
+// fourteen doubles fill seven columns, again an odd number (112 B).
+struct alignas(16) MomNbrU {
+    double x, y, z, ih;
+    double k11, k12, k13, k22, k23, k33;
+    double q;
+    double vx, vy, vz;
+};
+static_assert(sizeof(MomNbrU) == 112, "an odd number of 16-byte columns");
 // the reverse pass reads the factors unfolded (144 B)
 struct alignas(16) MomRec {
     double x, y, z, h;                     // position and smoothing length

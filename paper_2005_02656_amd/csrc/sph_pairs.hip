@@ -111,6 +111,42 @@ __device__ __forceinline__ MomNbr make_nbr(const RecSrc& R, int64_t a, const Pos
     return q;
 }
 
+__device__ __forceinline__ MomNbrU make_nbr_u(const RecSrc& R, int64_t a, const Pos4& pa,
+                                              double c11, double c12, double c13, double c22,
+                                              double c23, double c33)
+{
+    const MomNbr f = make_nbr(R, a, pa, c11, c12, c13, c22, c23, c33);
+    MomNbrU q;
+    q.x = f.x; q.y = f.y; q.z = f.z; q.ih = f.ih;
+    q.k11 = f.k11; q.k12 = f.k12; q.k13 = f.k13; q.k22 = f.k22; q.k23 = f.k23; q.k33 = f.k33;
+    q.q = f.q;
+    q.vx = f.vx; q.vy = f.vy; q.vz = f.vz;
+    return q;
+}
+
+// the record of slot a in the layout the uniformity flag selects
+__device__ __forceinline__ void put_nbr(const Domain* dom, void* rec, const RecSrc& R, int64_t a,
+                                        const Pos4& pa, double c11, double c12, double c13,
+                                        double c22, double c23, double c33)
+{
+    if (dom->nonuniform)
+        ((MomNbr*)rec)[a] = make_nbr(R, a, pa, c11, c12, c13, c22, c23, c33);
+    else
+        ((MomNbrU*)rec)[a] = make_nbr_u(R, a, pa, c11, c12, c13, c22, c23, c33);
+}
+
+__global__ void k_uniform_begin(Domain* d) { d->nonuniform = 0u; }
+
+// flags the step if any mass or sound speed differs from slot 0's
+__global__ __launch_bounds__(kBlock) void k_uniform_check(int64_t n, const double* __restrict__ m,
+                                                          const double* __restrict__ c,
+                                                          Domain* __restrict__ dom)
+{
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const bool diff = i < n && (m[i] != m[0] || c[i] != c[0]);
+    if (__ballot(diff) && (threadIdx.x & 63) == 0) atomicOr(&dom->nonuniform, 1u);
+}
+
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Params P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ list,
@@ -119,7 +155,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
                                                 double* __restrict__ c11, double* __restrict__ c12,
                                                 double* __restrict__ c13, double* __restrict__ c22,
                                                 double* __restrict__ c23, double* __restrict__ c33,
-                                                RecSrc R, MomNbr* __restrict__ rec)
+                                                RecSrc R, void* __restrict__ rec)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
@@ -182,22 +218,23 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
     }
     c11[a] = a11; c12[a] = a12; c13[a] = a13;
     c22[a] = a22; c23[a] = a23; c33[a] = a33;
-    if (rec) rec[a] = make_nbr(R, a, pa, a11, a12, a13, a22, a23, a33);
+    if (rec) put_nbr(dom, rec, R, a, pa, a11, a12, a13, a22, a23, a33);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pack_nbr(int64_t n, RecSrc R,
+__global__ __launch_bounds__(kBlock) void k_pack_nbr(int64_t n, const Domain* __restrict__ dom,
+                                                     RecSrc R,
                                                      const double* __restrict__ c11,
                                                      const double* __restrict__ c12,
                                                      const double* __restrict__ c13,
                                                      const double* __restrict__ c22,
                                                      const double* __restrict__ c23,
                                                      const double* __restrict__ c33,
-                                                     MomNbr* __restrict__ rec)
+                                                     void* __restrict__ rec)
 {
     int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (a < n)
-        rec[a] = make_nbr(R, a, Pos4{R.x[a], R.y[a], R.z[a], R.h[a]}, c11[a], c12[a], c13[a],
-                          c22[a], c23[a], c33[a]);
+        put_nbr(dom, rec, R, a, Pos4{R.x[a], R.y[a], R.z[a], R.h[a]}, c11[a], c12[a], c13[a],
+                c22[a], c23[a], c33[a]);
 }
 
 // the reverse pass's unfolded records, from the positions the IAD pass read
@@ -234,33 +271,36 @@ struct MomOut {
 
 __global__ void k_dtmin_begin(Domain* d) { d->dtmin_bits = ord_bits(INFINITY); }
 
-// what the target reads of itself beside its record: the unfolded factors
+// what the target reads of itself beside its record: the unfolded factors,
+// and h, m and c (the uniform record holds none of them)
 struct MomSelf {
-    const double *c11, *c12, *c13, *c22, *c23, *c33, *rho, *omega, *p;
+    const double *c11, *c12, *c13, *c22, *c23, *c33, *rho, *omega, *p, *h, *m, *c;
 };
 
-__global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
-                                                            const int32_t* __restrict__ nc,
-                                                            const int32_t* __restrict__ ns,
-                                                            const int32_t* __restrict__ list,
-                                                            const MomNbr* __restrict__ rec,
-                                                            MomSelf T,
-                                                            const double* __restrict__ u,
-                                                            MomOut O)
+// mass and sound speed of a neighbour: its own, or slot 0's in the uniform record
+SPH_DEV double nbr_m(const MomNbr& r, double) { return r.m; }
+SPH_DEV double nbr_c(const MomNbr& r, double) { return r.c; }
+SPH_DEV double nbr_m(const MomNbrU&, double m0) { return m0; }
+SPH_DEV double nbr_c(const MomNbrU&, double c0) { return c0; }
+template <class Rec>
+__device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restrict__ dom,
+                                                const int32_t* __restrict__ nc,
+                                                const int32_t* __restrict__ ns,
+                                                const int32_t* __restrict__ list,
+                                                const Rec* __restrict__ rec, const MomSelf& T,
+                                                const double* __restrict__ u, const MomOut& O,
+                                                int64_t a)
 {
-    const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    const int64_t lb = xcd_block(nb);
-    if (lb < 0) return;
-    const int64_t a = lb * kBlock + threadIdx.x;
     double dtc = INFINITY;
     if (a < P.n) {
-        const MomNbr ra = rec[a];
-        const double xa = ra.x, ya = ra.y, za = ra.z, ha = ra.h;
+        const Rec ra = rec[a];
+        const double m0 = T.m[0], c0 = T.c[0];
+        const double xa = ra.x, ya = ra.y, za = ra.z, ha = T.h[a];
         const double vxa = ra.vx, vya = ra.vy, vza = ra.vz;
         const double ca11 = T.c11[a], ca12 = T.c12[a], ca13 = T.c13[a];
         const double ca22 = T.c22[a], ca23 = T.c23[a], ca33 = T.c33[a];
         const double rho_a = T.rho[a];
-        const double ca = ra.c, ira = 1.0 / rho_a;
+        const double ca = nbr_c(ra, c0), ira = 1.0 / rho_a;
         const double pa_ = T.p[a] / (T.omega[a] * rho_a * rho_a);   // P/(Omega rho^2)
         const double tsa = kPiHalfSq / (ha * ha);
         const double w0a = P.bn / (ha * ha * ha);
@@ -280,7 +320,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
                 e[u] = (k < total) ? list[lpos(a, j, ng)] : -1;
             }
         };
-        auto pair = [&](bool gather, const MomNbr& rb) {
+        auto pair = [&](bool gather, const Rec& rb) {
 #if SPH_PAIR_CONTRACT
             // the pair terms may fuse multiply-adds (rounding-level changes
             // only); r^2 itself comes from disp(), which never contracts
@@ -308,11 +348,11 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             double hPi = 0.0;   // Pi_ab / 2
             if (xv < 0.0) {
                 const double w = xv * rsqrt_nr(r2);
-                const double vsig = ca + rb.c - 3.0 * w;
+                const double vsig = ca + nbr_c(rb, c0) - 3.0 * w;
                 hPi = -0.25 * al * vsig * w;
             }
             // a_a -= m_b (pb_a + Pi/(2 rho_a)) A_ab(h_a) + (q_b + Pi/2) W_b K_b d
-            const double mb = rb.m;
+            const double mb = nbr_m(rb, m0);
             const double sa = mb * (pa_ + hPi * ira);
             const double sb = (rb.q + hPi) * Wb;
             axs -= sa * Aax + sb * Kx;
@@ -331,7 +371,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
         entries(0, nx);
         for (int k0 = 0; k0 < total; k0 += kMomBatch) {
             bool ok[kMomBatch];
-            MomNbr rb[kMomBatch];
+            Rec rb[kMomBatch];
 #pragma unroll
             for (int u = 0; u < kMomBatch; ++u) {
                 ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
@@ -361,10 +401,30 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
             if (qu < dtc) dtc = qu;
         }
     }
-    // block minimum of the candidates, one atomic per wavefront
+    // wavefront minimum of the candidates, then the global one
     for (int o = 32; o > 0; o >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, o, 64));
     if ((threadIdx.x & 63) == 0 && dtc < INFINITY)
         ord_min_to(&dom->dtmin_bits, dtc);
+}
+
+// the record layout the uniformity flag selected when the records were written
+__global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
+                                                            const int32_t* __restrict__ nc,
+                                                            const int32_t* __restrict__ ns,
+                                                            const int32_t* __restrict__ list,
+                                                            const void* __restrict__ rec,
+                                                            MomSelf T,
+                                                            const double* __restrict__ u,
+                                                            MomOut O)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    if (dom->nonuniform)
+        momentum_energy(P, dom, nc, ns, list, (const MomNbr*)rec, T, u, O, a);
+    else
+        momentum_energy(P, dom, nc, ns, list, (const MomNbrU*)rec, T, u, O, a);
 }
 
 __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals* g)
@@ -408,9 +468,13 @@ hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particl
     }
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.p4, W.vol, W.pv);
+    if (write_rec) {
+        k_uniform_begin<<<1, 1, 0, s>>>(W.dom);
+        k_uniform_check<<<nb, kBlock, 0, s>>>(P.n, p->m, p->c, W.dom);
+    }
     k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12,
                                           p->c13, p->c22, p->c23, p->c33, rec_src(p),
-                                          write_rec ? (MomNbr*)W.rec : nullptr);
+                                          write_rec ? (void*)W.rec : nullptr);
     return hipGetLastError();
 }
 
@@ -429,14 +493,17 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
     if (pack) {
         hipError_t e = launch_pack_p4(P, W, p, s);
         if (e != hipSuccess) return e;
-        k_pack_nbr<<<nb, kBlock, 0, s>>>(P.n, rec_src(p), p->c11, p->c12, p->c13, p->c22,
-                                         p->c23, p->c33, (MomNbr*)W.rec);
+        k_uniform_begin<<<1, 1, 0, s>>>(W.dom);
+        k_uniform_check<<<nb, kBlock, 0, s>>>(P.n, p->m, p->c, W.dom);
+        k_pack_nbr<<<nb, kBlock, 0, s>>>(P.n, W.dom, rec_src(p), p->c11, p->c12, p->c13,
+                                         p->c22, p->c23, p->c33, (void*)W.rec);
     }
     MomOut O{p->ax, p->ay, p->az, p->du};
-    MomSelf T{p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p};
+    MomSelf T{p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p,
+              p->h, p->m, p->c};
     k_dtmin_begin<<<1, 1, 0, s>>>(W.dom);
     k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list,
-                                                      (const MomNbr*)W.rec, T, p->u, O);
+                                                      (const void*)W.rec, T, p->u, O);
     return hipGetLastError();
 }
 

@@ -24,9 +24,11 @@ def test_more_than_one_gpu_exits_with_a_message():
 def test_byte_model_per_phase():
     k_g, k_s, k_c = 91.7, 91.8, 121.5
     bpp = lambda ph, **kw: bench.bytes_per_particle(ph, k_g, k_s, True, k_c, 2, **kw)
-    # momentum: the target's 144-byte record and unfolded C rho omega p, u, the
-    # two counts, the list, four outputs
-    assert bpp("momentum_energy") == pytest.approx(144 + 72 + 8 + 8 + 4 * k_s + 32)
+    # momentum: the target's 144-byte record and unfolded C rho omega p h, u, the
+    # two counts, the list, four outputs; 112-byte records with equal m and c
+    assert bpp("momentum_energy") == pytest.approx(144 + 80 + 8 + 8 + 4 * k_s + 32)
+    assert bpp("momentum_energy") - bpp("momentum_energy", urec=True) == 32
+    assert bpp("iad") - bpp("iad", urec=True) == 32
     # the candidate lists are read once per Newton iteration
     assert bpp("newton_h") == pytest.approx(40 + 8 * k_c)
     # with the fused step the density is formed in the list filter

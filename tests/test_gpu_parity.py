@@ -16,6 +16,15 @@ from gpu_support import Run, configs, oracle_pairs, rel_err
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
+def _mass_jitter(w, seed=7, rel=0.02):
+    """w with masses varied by up to rel: the momentum pass then keeps m and c
+    in its neighbour records (with equal masses and the weakly compressible EOS
+    it takes them from slot 0)."""
+    rng = np.random.default_rng(seed)
+    w.arrays["m"] = w.arrays["m"] * (1.0 + rel * rng.uniform(-1.0, 1.0, w.n))
+    return w
+
+
 CASES = {
     # periodic lattice with jittered velocities (the C1 shape, smaller)
     "lattice12": lambda: inputs.lattice(12, seed=1, sigma_v=0.01),
@@ -25,6 +34,8 @@ CASES = {
     "blob": lambda: inputs.gaussian_blob(20000, seed=3, seed_v=33),
     # rotating square patch: open x, y; periodic z; weakly compressible EOS
     "patch": lambda: inputs.square_patch(14),
+    # the same with unequal masses
+    "patch_mvar": lambda: _mass_jitter(inputs.square_patch(14)),
 }
 NG = 400
 
