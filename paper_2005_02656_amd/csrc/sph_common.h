@@ -566,6 +566,10 @@ hipError_t launch_density(const Params& P, const Layout& L, const Ws& W, sph_par
 // write_rec: also fill the momentum records (sph_step), else momentum packs them
 hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particles* p,
                       hipStream_t s, bool pack, bool write_rec);
+// sets Domain::nonuniform if any m or c differs from slot 0's (before the
+// momentum records are written: it selects their layout)
+hipError_t launch_uniform_check(const Params& P, const Ws& W, const sph_particles* p,
+                                hipStream_t s);
 // the unfolded 144-byte records the reverse pass reads (over the step's MomNbr)
 hipError_t launch_pack_rec(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s);
 hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,

@@ -11,8 +11,8 @@
 // 3x3 inversion, the integrator and the global sums stay in FP64.
 //
 // Gathered bytes per neighbour: 16 (position) + 4 (mass or volume) in the
-// density and IAD passes, one 80-byte record in the momentum pass (FP64: 32 +
-// 8, 32 and 144).
+// density and IAD passes, one 80-byte record in the momentum pass, or 16 + 48
+// bytes with equal masses and sound speeds (FP64: 32 + 8, 32, and 144 or 112).
 #include "sph_common.h"
 
 namespace sph {
@@ -34,6 +34,15 @@ struct alignas(16) RecM {
     float q, c, m, ih;
     float vx, vy, vz;
     float spare[3];
+};
+
+// the same factors when every mass and sound speed is equal (m and c from
+// slot 0), without the position: three columns, read with the 16-byte PosM
+struct alignas(16) RecMU {
+    float k11, k12, k13, k22, k23, k33;
+    float q, ih;
+    float vx, vy, vz;
+    float spare;
 };
 
 struct CellGeom {
@@ -227,6 +236,26 @@ __device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, const Pos
     return q;
 }
 
+__device__ __forceinline__ RecMU make_recmu(const RecM& f)
+{
+    RecMU q;
+    q.k11 = f.k11; q.k12 = f.k12; q.k13 = f.k13; q.k22 = f.k22; q.k23 = f.k23; q.k33 = f.k33;
+    q.q = f.q; q.ih = f.ih;
+    q.vx = f.vx; q.vy = f.vy; q.vz = f.vz;
+    q.spare = 0.0f;
+    return q;
+}
+
+// the record of slot a in the layout the uniformity flag selects
+__device__ __forceinline__ void put_recm(const Domain* dom, void* rec, const RecSrcM& R,
+                                         int64_t a, const PosM& pa, double c11, double c12,
+                                         double c13, double c22, double c23, double c33)
+{
+    const RecM f = make_recm(R, a, pa, c11, c12, c13, c22, c23, c33);
+    if (dom->nonuniform) ((RecM*)rec)[a] = f;
+    else ((RecMU*)rec)[a] = make_recmu(f);
+}
+
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m(Params P, Domain* __restrict__ dom,
                                                   const int32_t* __restrict__ nc,
                                                   const int32_t* __restrict__ list,
@@ -236,7 +265,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
                                                   double* __restrict__ c11, double* __restrict__ c12,
                                                   double* __restrict__ c13, double* __restrict__ c22,
                                                   double* __restrict__ c23, double* __restrict__ c33,
-                                                  RecSrcM R, RecM* __restrict__ rec)
+                                                  RecSrcM R, void* __restrict__ rec)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
@@ -303,10 +332,11 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
     }
     c11[a] = a11; c12[a] = a12; c13[a] = a13;
     c22[a] = a22; c23[a] = a23; c33[a] = a33;
-    if (rec) rec[a] = make_recm(R, a, pa, a11, a12, a13, a22, a23, a33);
+    if (rec) put_recm(dom, rec, R, a, pa, a11, a12, a13, a22, a23, a33);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pack_recm(int64_t n, RecSrcM R,
+__global__ __launch_bounds__(kBlock) void k_pack_recm(int64_t n, const Domain* __restrict__ dom,
+                                                      RecSrcM R,
                                                       const PosM* __restrict__ pm,
                                                       const double* __restrict__ c11,
                                                       const double* __restrict__ c12,
@@ -314,10 +344,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_recm(int64_t n, RecSrcM R,
                                                       const double* __restrict__ c22,
                                                       const double* __restrict__ c23,
                                                       const double* __restrict__ c33,
-                                                      RecM* __restrict__ rec)
+                                                      void* __restrict__ rec)
 {
     int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (a < n) rec[a] = make_recm(R, a, pm[a], c11[a], c12[a], c13[a], c22[a], c23[a], c33[a]);
+    if (a < n) put_recm(dom, rec, R, a, pm[a], c11[a], c12[a], c13[a], c22[a], c23[a], c33[a]);
 }
 
 struct MomOutM {
@@ -328,29 +358,49 @@ __global__ void k_dtmin_begin_m(Domain* d) { d->dtmin_bits = ord_bits(INFINITY);
 
 // what the target reads of itself beside its record (FP64 arrays)
 struct MomSelfM {
-    const double *h, *c, *c11, *c12, *c13, *c22, *c23, *c33, *rho, *omega, *p;
+    const double *h, *c, *c11, *c12, *c13, *c22, *c23, *c33, *rho, *omega, *p, *m;
 };
 
 __device__ __forceinline__ PosM rec_pos(const RecM& r) { return PosM{r.ox, r.oy, r.oz, r.cpack}; }
 
-__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momentum_energy_m(Params P, Domain* __restrict__ dom,
-                                                              const int32_t* __restrict__ nc,
-                                                              const int32_t* __restrict__ ns,
-                                                              const int32_t* __restrict__ list,
-                                                              const RecM* __restrict__ rec,
-                                                              MomSelfM T,
-                                                              const double* __restrict__ u,
-                                                              MomOutM O)
+// a neighbour's record and position: one 80-byte record, or with equal masses
+// and sound speeds the 48-byte record and the 16-byte position record
+struct NbrM {
+    const RecM* rec;
+    const RecMU* recu;
+    const PosM* pm;
+};
+SPH_DEV void load_nbr(const NbrM& N, int32_t b, RecM& r, PosM& q)
 {
-    const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    const int64_t lb = xcd_block(nb);
-    if (lb < 0) return;
-    const int64_t a = lb * kBlock + threadIdx.x;
+    r = N.rec[b];
+    q = rec_pos(r);
+}
+SPH_DEV void load_nbr(const NbrM& N, int32_t b, RecMU& r, PosM& q)
+{
+    r = N.recu[b];
+    q = N.pm[b];
+}
+SPH_DEV float nbr_m(const RecM& r, float) { return r.m; }
+SPH_DEV float nbr_c(const RecM& r, float) { return r.c; }
+SPH_DEV float nbr_m(const RecMU&, float m0) { return m0; }
+SPH_DEV float nbr_c(const RecMU&, float c0) { return c0; }
+
+template <class Rec>
+__device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __restrict__ dom,
+                                                  const int32_t* __restrict__ nc,
+                                                  const int32_t* __restrict__ ns,
+                                                  const int32_t* __restrict__ list,
+                                                  const NbrM& N, const MomSelfM& T,
+                                                  const double* __restrict__ u,
+                                                  const MomOutM& O, int64_t a)
+{
     double dtc = INFINITY;
     if (a < P.n) {
         const CellGeom g = cell_geom(P, *dom);
-        const RecM ra = rec[a];
-        const PosM pa = rec_pos(ra);
+        Rec ra;
+        PosM pa;
+        load_nbr(N, (int32_t)a, ra, pa);
+        const float m0 = (float)T.m[0], c0 = (float)T.c[0];   // the uniform record's m, c
         const double ha = T.h[a];
         const float tsa = (float)(kPiHalfSq / (ha * ha));
         const float w0a = (float)(P.bn / (ha * ha * ha));
@@ -358,7 +408,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
         const float al = (float)P.alpha;
         const double rho_a = T.rho[a];
         const float pa_ = (float)(T.p[a] / (T.omega[a] * rho_a * rho_a));   // P/(Omega rho^2)
-        const float ira = (float)(1.0 / rho_a), ca = ra.c;
+        const float ira = (float)(1.0 / rho_a), ca = nbr_c(ra, c0);
         const float ca11 = (float)T.c11[a], ca12 = (float)T.c12[a], ca13 = (float)T.c13[a];
         const float ca22 = (float)T.c22[a], ca23 = (float)T.c23[a], ca33 = (float)T.c33[a];
         const int ng = P.ng_max;
@@ -381,11 +431,12 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
         entries(0, nx);
         for (int k0 = 0; k0 < total; k0 += kB) {
             bool okv[kB];
-            RecM rbv[kB];
+            Rec rbv[kB];
+            PosM qv[kB];
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
                 okv[u] = (uint32_t)nx[u] < (uint32_t)P.n;
-                rbv[u] = rec[okv[u] ? nx[u] : (int32_t)a];
+                load_nbr(N, okv[u] ? nx[u] : (int32_t)a, rbv[u], qv[u]);
             }
             entries(k0 + kB, nx);
 #pragma unroll
@@ -393,9 +444,9 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
 #pragma clang fp contract(fast)
             if (!okv[u]) continue;
             const bool gather = k0 + u < cg;
-            const RecM& rb = rbv[u];
+            const Rec& rb = rbv[u];
             float dx, dy, dz;
-            const float r2 = disp_m(g, pa, rec_pos(rb), dx, dy, dz);
+            const float r2 = disp_m(g, pa, qv[u], dx, dy, dz);
             float Wa = 0.0f;
             if (gather) Wa = w0a * sinc_S_f(r2 * tsa, P.sinc_n);
             // support of W(h_b): v_b < 2, i.e. t_b < pi^2
@@ -414,10 +465,10 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
             float hPi = 0.0f;   // Pi_ab / 2
             if (xv < 0.0f) {
                 const float w = xv * rsqrtf(r2);
-                const float vsig = ca + rb.c - 3.0f * w;
+                const float vsig = ca + nbr_c(rb, c0) - 3.0f * w;
                 hPi = -0.25f * al * vsig * w;
             }
-            const float mb = rb.m;
+            const float mb = nbr_m(rb, m0);
             const float sa = mb * (pa_ + hPi * ira);
             const float sb = (rb.q + hPi) * Wb;
             axs += (double)(-(sa * Aax + sb * Kx));
@@ -454,6 +505,25 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
         ord_min_to(&dom->dtmin_bits, dtc);
 }
 
+// the record layout the uniformity flag selected when the records were written
+__global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momentum_energy_m(Params P, Domain* __restrict__ dom,
+                                                              const int32_t* __restrict__ nc,
+                                                              const int32_t* __restrict__ ns,
+                                                              const int32_t* __restrict__ list,
+                                                              NbrM N, MomSelfM T,
+                                                              const double* __restrict__ u,
+                                                              MomOutM O)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    if (dom->nonuniform)
+        momentum_energy_m<RecM>(P, dom, nc, ns, list, N, T, u, O, a);
+    else
+        momentum_energy_m<RecMU>(P, dom, nc, ns, list, N, T, u, O, a);
+}
+
 RecSrcM recm_src(const sph_particles* p)
 {
     return RecSrcM{p->m, p->rho, p->omega, p->p, p->c, p->vx, p->vy, p->vz, p->h};
@@ -464,6 +534,7 @@ RecSrcM recm_src(const sph_particles* p)
 static_assert(sizeof(PosM) == 16, "PosM layout");
 static_assert(sizeof(RecM) == 80, "RecM layout");
 static_assert(sizeof(RecM) <= sizeof(MomRec), "RecM records alias the MomRec area");
+static_assert(sizeof(RecMU) == 48, "RecMU layout: an odd number of 16-byte columns");
 size_t mixed_posm_bytes() { return sizeof(PosM); }
 size_t mixed_rec_bytes() { return sizeof(RecM); }
 
@@ -496,10 +567,11 @@ hipError_t launch_iad_mixed(const Params& P, const Layout& L, const Ws& W, sph_p
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     PosM* pm = (PosM*)W.posm;
     if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
+    if (write_rec) launch_uniform_check(P, W, p, s);
     k_volume_m<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.mf2);
     k_iad_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, pm, W.mf2, p->h, p->c11,
                                             p->c12, p->c13, p->c22, p->c23, p->c33, recm_src(p),
-                                            write_rec ? (RecM*)W.recm : nullptr);
+                                            write_rec ? W.recm : nullptr);
     return hipGetLastError();
 }
 
@@ -508,16 +580,18 @@ hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const 
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     PosM* pm = (PosM*)W.posm;
-    RecM* rec = (RecM*)W.recm;
     if (pack) {
         k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
-        k_pack_recm<<<nb, kBlock, 0, s>>>(P.n, recm_src(p), pm, p->c11, p->c12, p->c13,
-                                          p->c22, p->c23, p->c33, rec);
+        launch_uniform_check(P, W, p, s);
+        k_pack_recm<<<nb, kBlock, 0, s>>>(P.n, W.dom, recm_src(p), pm, p->c11, p->c12, p->c13,
+                                          p->c22, p->c23, p->c33, W.recm);
     }
     MomOutM O{p->ax, p->ay, p->az, p->du};
-    MomSelfM T{p->h, p->c, p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p};
+    MomSelfM T{p->h, p->c, p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p,
+               p->m};
+    NbrM N{(const RecM*)W.recm, (const RecMU*)W.recm, pm};
     k_dtmin_begin_m<<<1, 1, 0, s>>>(W.dom);
-    k_momentum_energy_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, rec, T,
+    k_momentum_energy_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, N, T,
                                                         p->u, O);
     return hipGetLastError();
 }

@@ -468,13 +468,19 @@ hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particl
     }
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.p4, W.vol, W.pv);
-    if (write_rec) {
-        k_uniform_begin<<<1, 1, 0, s>>>(W.dom);
-        k_uniform_check<<<nb, kBlock, 0, s>>>(P.n, p->m, p->c, W.dom);
-    }
+    if (write_rec) launch_uniform_check(P, W, p, s);
     k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12,
                                           p->c13, p->c22, p->c23, p->c33, rec_src(p),
                                           write_rec ? (void*)W.rec : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform_check(const Params& P, const Ws& W, const sph_particles* p,
+                                hipStream_t s)
+{
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    k_uniform_begin<<<1, 1, 0, s>>>(W.dom);
+    k_uniform_check<<<nb, kBlock, 0, s>>>(P.n, p->m, p->c, W.dom);
     return hipGetLastError();
 }
 
@@ -493,8 +499,7 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
     if (pack) {
         hipError_t e = launch_pack_p4(P, W, p, s);
         if (e != hipSuccess) return e;
-        k_uniform_begin<<<1, 1, 0, s>>>(W.dom);
-        k_uniform_check<<<nb, kBlock, 0, s>>>(P.n, p->m, p->c, W.dom);
+        launch_uniform_check(P, W, p, s);
         k_pack_nbr<<<nb, kBlock, 0, s>>>(P.n, W.dom, rec_src(p), p->c11, p->c12, p->c13,
                                          p->c22, p->c23, p->c33, (void*)W.rec);
     }
