@@ -313,14 +313,21 @@ def test_fused_candidates_cover_reach(name):
     assert any(ok), name
 
 
+@pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("per", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1),
                                  (1, 0, 1), (0, 1, 1)])
-def test_fused_step_periodic_patterns(per):
-    """The candidate walk is compiled once per pattern of periodic axes; every
-    pattern gives the oracle's h, lists and density (the all-periodic pattern is
-    covered by the cases above)."""
+def test_fused_step_periodic_patterns(per, uniform):
+    """The candidate walk, Newton, the filter and the momentum pass are compiled
+    once per pattern of periodic axes; every pattern gives the oracle's h,
+    lists, density and rates (the all-periodic pattern is covered by the cases
+    above).  uniform: equal masses and internal energies, so equal sound speeds
+    and the momentum pass's short records."""
     w0 = inputs.random_periodic(1500, seed=9, h_lo=0.08, h_hi=0.10)
-    w = inputs.Workload(w0.name, w0.arrays, {**w0.params, "periodic": per})
+    arr = dict(w0.arrays)
+    if uniform:
+        arr["m"] = np.full(w0.n, np.mean(arr["m"]))
+        arr["u"] = np.full(w0.n, np.mean(arr["u"]))
+    w = inputs.Workload(w0.name, arr, {**w0.params, "periodic": per})
     cfg, ocfg = configs(w, ng_max=NG)
     a = w.arrays
     r = Run(w, cfg)
@@ -332,6 +339,12 @@ def test_fused_step_periodic_patterns(per):
     nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, a["x"], a["y"], a["z"], h_o)
     assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
     assert np.array_equal(P, oracle_pairs(lists, gath))
-    rho_o, om_o, _, _ = oracle.density(ocfg, a["x"], a["y"], a["z"], h_o, a["m"], a["u"])
+    rho_o, om_o, p_o, c_o = oracle.density(ocfg, a["x"], a["y"], a["z"], h_o, a["m"], a["u"])
     assert rel_err(r.by_id("rho"), rho_o) < TOL
     assert rel_err(r.by_id("omega"), om_o) < TOL
+    Cm, _ = oracle.iad(ocfg, a["x"], a["y"], a["z"], h_o, a["m"], rho_o)
+    me = oracle.momentum_energy(ocfg, a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"], h_o,
+                                a["m"], rho_o, om_o, p_o, c_o, Cm)
+    for f in ("ax", "ay", "az"):
+        assert rel_err(r.by_id(f), me[f], me["scale_a"]) < TOL, f
+    assert rel_err(r.by_id("du"), me["du"], me["scale_du"]) < TOL
