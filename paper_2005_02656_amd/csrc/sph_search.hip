@@ -349,6 +349,7 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
     const Domain D = *dom;
     const Pos4 pa = p4[a];
     const Pos4f fa = pf[a];
+    const uint32_t far2 = __float_as_uint(kFull ? fa.r2 * sc : fa.r2);
     const double hmax0 = ord_value(D.hmax_new_bits);
     const int cap = P.cand_cap;
     // candidates are staged in LDS, column per lane, and written out in
@@ -374,10 +375,12 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
                 if (kPer & (1 << c)) d[c] = fmaf(-P.wrapL[c], rintf(d[c] * P.wrapInvL[c]), d[c]);
             const float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             // r < 2 kap max(h_a, h_b) (+ slack): r^2 below either widened
-            // squared reach (the full pass scales the short ones up by sc)
-            bool near;
-            if (kFull) near = (r2 < fa.r2 * sc) | (r2 < q.r2 * sc);
-            else near = (r2 < fa.r2) | (r2 < q.r2);
+            // squared reach (the full pass scales the short ones up by sc).
+            // All three are non-negative floats, whose order is that of their
+            // bit patterns as unsigned integers: one integer max and one
+            // compare (a float max quiets NaNs first, one more instruction).
+            const float qr2 = kFull ? q.r2 * sc : q.r2;
+            const bool near = __float_as_uint(r2) < max(far2, __float_as_uint(qr2));
             if (near & (b != self)) {
                 if (k < cap) {
                     stage[k & 7][t] = b;
