@@ -146,6 +146,8 @@ def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload, fused, urec=False):
     by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters, fused, urec)
     hbm = by * n / t / 1e9
     kern = PHASE_KERNEL[dom]
+    if dom == "momentum_energy" and urec:
+        kern = "k_momentum_energy_u"   # the kernel of the 112-byte records
     res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom],
            "traffic": traffic_from_profile(kern, workload)}
     pairs = {"newton_h": iters * k_c * n, "density": k_g * n, "lists": k_g * n,

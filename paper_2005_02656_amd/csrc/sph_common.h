@@ -475,6 +475,9 @@ SPH_DEV double sinc_S(double t, int n)
 #ifndef SPH_MOM_ATTR
 #define SPH_MOM_ATTR SPH_WAVES_CAP(SPH_WAVES_MOM)
 #endif
+#ifndef SPH_MOM_U_ATTR
+#define SPH_MOM_U_ATTR SPH_WAVES_EXACT(3)
+#endif
 #ifndef SPH_WAVES_CAND
 #define SPH_WAVES_CAND 7
 #endif
@@ -525,6 +528,10 @@ SPH_DEV void finish_density(const Params& P, Domain* dom, const DensOut& O, int6
 // neighbours whose records the momentum/energy loops load before computing
 #ifndef SPH_MOM_BATCH
 #define SPH_MOM_BATCH 4
+#endif
+// the momentum pass over 112-byte records: batches of 3 at three wavefronts
+#ifndef SPH_MOM_U_BATCH
+#define SPH_MOM_U_BATCH 3
 #endif
 
 // neighbour loops load this many neighbours' records before computing on them

@@ -282,7 +282,7 @@ SPH_DEV double nbr_m(const MomNbr& r, double) { return r.m; }
 SPH_DEV double nbr_c(const MomNbr& r, double) { return r.c; }
 SPH_DEV double nbr_m(const MomNbrU&, double m0) { return m0; }
 SPH_DEV double nbr_c(const MomNbrU&, double c0) { return c0; }
-template <class Rec>
+template <class Rec, int kMomBatch>
 __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ ns,
@@ -310,7 +310,6 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
         const int co = min(ns[a] - nc[a], ng);
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
-        constexpr int kMomBatch = SPH_MOM_BATCH;
         // list entries of the batch starting at k0 (-1 past the end)
         auto entries = [&](int k0, int32_t (&e)[kMomBatch]) {
 #pragma unroll
@@ -407,24 +406,43 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
         ord_min_to(&dom->dtmin_bits, dtc);
 }
 
-// the record layout the uniformity flag selected when the records were written
+// One kernel per record layout; both are launched and the one the uniformity
+// flag did not select returns at once.  The 112-byte records leave room for a
+// third wavefront per SIMD with batches of 3 (52.7 ms against 54.9 at two
+// wavefronts and batches of 4, 64 M particles); the 144-byte records spill
+// at three.
 __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
                                                             const int32_t* __restrict__ list,
-                                                            const void* __restrict__ rec,
+                                                            const MomNbr* __restrict__ rec,
                                                             MomSelf T,
                                                             const double* __restrict__ u,
                                                             MomOut O)
 {
+    if (dom->nonuniform == 0u) return;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
-    if (dom->nonuniform)
-        momentum_energy(P, dom, nc, ns, list, (const MomNbr*)rec, T, u, O, a);
-    else
-        momentum_energy(P, dom, nc, ns, list, (const MomNbrU*)rec, T, u, O, a);
+    momentum_energy<MomNbr, SPH_MOM_BATCH>(P, dom, nc, ns, list, rec, T, u, O, a);
+}
+
+__global__ __launch_bounds__(kBlock) SPH_MOM_U_ATTR void k_momentum_energy_u(Params P, Domain* __restrict__ dom,
+                                                                const int32_t* __restrict__ nc,
+                                                                const int32_t* __restrict__ ns,
+                                                                const int32_t* __restrict__ list,
+                                                                const MomNbrU* __restrict__ rec,
+                                                                MomSelf T,
+                                                                const double* __restrict__ u,
+                                                                MomOut O)
+{
+    if (dom->nonuniform != 0u) return;
+    const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    const int64_t lb = xcd_block(nb);
+    if (lb < 0) return;
+    const int64_t a = lb * kBlock + threadIdx.x;
+    momentum_energy<MomNbrU, SPH_MOM_U_BATCH>(P, dom, nc, ns, list, rec, T, u, O, a);
 }
 
 __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals* g)
@@ -507,8 +525,10 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
     MomSelf T{p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p,
               p->h, p->m, p->c};
     k_dtmin_begin<<<1, 1, 0, s>>>(W.dom);
+    k_momentum_energy_u<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list,
+                                                        (const MomNbrU*)W.rec, T, p->u, O);
     k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list,
-                                                      (const void*)W.rec, T, p->u, O);
+                                                      (const MomNbr*)W.rec, T, p->u, O);
     return hipGetLastError();
 }
 

@@ -57,11 +57,16 @@ def test_roofline_reports_the_binding_ceiling():
     r2 = bench.roofline({"build_cells": 50.0, "integrate": 1.0}, n, k_g, k_s, True, 2, k_c,
                         "c4", True)
     assert r2["bound"] == "hbm" and "alt" not in r2
+    # with equal masses and sound speeds the momentum phase runs its own kernel
+    r3 = bench.roofline(phases, n, k_g, k_s, True, 2, k_c, "c4", True, urec=True)
+    assert r3["kernel"] == "k_momentum_energy_u"
 
 
 def test_traffic_comes_from_a_summary_of_the_current_sources(tmp_path):
-    s = profiling.read_summary(os.path.join(ROOT, "profiles", "k_momentum_energy_c4.md"))
-    t = bench.traffic_from_profile("k_momentum_energy", "c4")
+    # C4 has equal masses under the weakly compressible EOS: 112-byte records
+    s = profiling.read_summary(os.path.join(ROOT, "profiles", "k_momentum_energy_u_c4.md"))
+    assert s, "no committed summary for the C4 momentum kernel"
+    t = bench.traffic_from_profile("k_momentum_energy_u", "c4")
     if s.get("source_digest") == profiling.source_digest():
         assert t == pytest.approx(float(s["fetch_bytes_per_launch"])
                                   + float(s["write_bytes_per_launch"]))
