@@ -45,6 +45,7 @@ __global__ void k_domain_begin(Domain* d)
         d->ord_max[k] = 0ull;
     }
     d->ord_hmax = 0ull;
+    d->mass_varies = 0u;
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -61,14 +62,20 @@ __device__ __forceinline__ double wave_max(double v)
 __global__ __launch_bounds__(kBlock) void k_bbox(const double* __restrict__ x,
                                                  const double* __restrict__ y,
                                                  const double* __restrict__ z,
-                                                 const double* __restrict__ h, int64_t n,
+                                                 const double* __restrict__ h,
+                                                 const double* __restrict__ m, int64_t n,
                                                  Domain* d)
 {
     double mn[3] = {INFINITY, INFINITY, INFINITY};
     double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    // whether every mass equals slot 0's (the density sums then skip the
+    // mass gather); the order of the slots does not matter
+    const double m0 = m[0];
+    bool mv = false;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
         double px = x[i], py = y[i], pz = z[i], ph = h[i];
+        mv |= m[i] != m0;
         mn[0] = fmin(mn[0], px); mx[0] = fmax(mx[0], px);
         mn[1] = fmin(mn[1], py); mx[1] = fmax(mx[1], py);
         mn[2] = fmin(mn[2], pz); mx[2] = fmax(mx[2], pz);
@@ -76,6 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const double* __restrict__ x,
     }
     __shared__ double s[kWaves][7];
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (__ballot(mv) && lane == 0) atomicOr(&d->mass_varies, 1u);
     double r[7];
     for (int k = 0; k < 3; ++k) r[k] = wave_min(mn[k]);
     for (int k = 0; k < 4; ++k) r[3 + k] = wave_max(mx[k]);
@@ -424,7 +432,7 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
     const int64_t nb = (n + kBlock - 1) / kBlock;
     k_domain_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t rg = nb < kRedGrid ? nb : kRedGrid;
-    k_bbox<<<rg, kBlock, 0, s>>>(p->x, p->y, p->z, p->h, n, W.dom);
+    k_bbox<<<rg, kBlock, 0, s>>>(p->x, p->y, p->z, p->h, p->m, n, W.dom);
     k_domain_end<<<1, 1, 0, s>>>(P, W.dom);
     k_keys<<<nb, kBlock, 0, s>>>(p->x, p->y, p->z, n, W.dom, W.keys0, W.idx0);
 

@@ -66,6 +66,7 @@ struct Domain {
     uint32_t err;              // sticky SPH_ERRBIT_* word
     uint32_t refit;            // fused step: an h left the short candidate reach
     uint32_t nonuniform;       // some m or c differs from slot 0's (full momentum records)
+    uint32_t mass_varies;      // some m differs from slot 0's (set by the cell build)
     float walk_slack;          // 2^-20 x the largest extent (FP32 candidate walk)
     int64_t built_n;
 };

@@ -605,16 +605,30 @@ __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Dom
         sS = O.m[a];          // self term: S = 1, v dS/dv = 0
         sD = 3.0 * O.m[a];
     }
+    // with equal masses (flagged by the cell build) the mass of every
+    // neighbour is slot 0's: no gather
+    const bool mvar = !kDens || dom->mass_varies != 0u;
+    const double m0 = kDens ? O.m[0] : 0.0;
     int cg = 0, co = 0;
     for (int j0 = 0; j0 < cntl; j0 += 8) {
         int32_t bb[8];
         load_chunk_or_self(cand, a, j0, cap, cnt, bb);
         Pos4 q[8];
         double mb[8];
+        // one straight run of loads per case (a test per load would split the
+        // batch into blocks and serialise its gathers)
+        if (mvar) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            q[u] = pair_gather32(p4, bb[u], odd);
-            if (kDens) mb[u] = O.m[bb[u]];
+            for (int u = 0; u < 8; ++u) {
+                q[u] = pair_gather32(p4, bb[u], odd);
+                if (kDens) mb[u] = O.m[bb[u]];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                q[u] = pair_gather32(p4, bb[u], odd);
+                mb[u] = m0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
