@@ -229,8 +229,8 @@ def cpu_baseline(side):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library "
+              "has no multi-GPU decomposition", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2005_02656_amd import inputs, sph
