@@ -6,7 +6,8 @@
 // per-particle sums in FP64.  Positions are an FP64 cell origin (the cell of
 // the last build, recovered from a packed integer cell index) plus an FP32
 // offset, so a pair displacement is (cell difference x cell edge) + (offset
-// difference) in FP32 with the minimum image taken on cell indices.  The
+// difference) in FP32 with the minimum image taken on cell indices
+// (axis_disp, sph_mixed_geom.h).  The
 // neighbour test that builds the lists, the Newton update of h, the EOS, the
 // 3x3 inversion, the integrator and the global sums stay in FP64.
 //
@@ -14,6 +15,7 @@
 // density and IAD passes, one 80-byte record in the momentum pass, or 16 + 48
 // bytes with equal masses and sound speeds (FP64: 32 + 8, 32, and 144 or 112).
 #include "sph_common.h"
+#include "sph_mixed_geom.h"
 
 namespace sph {
 namespace {
@@ -60,17 +62,6 @@ __device__ __forceinline__ CellGeom cell_geom(const Params& P, const Domain& D)
     }
     g.nax = D.ncell_axis;
     return g;
-}
-
-__device__ __forceinline__ float axis_disp(int ca, int cb, float oa, float ob, float ce, bool per,
-                                           int nax)
-{
-    int dc = cb - ca;
-    if (per) {
-        if (dc > nax / 2) dc -= nax;
-        else if (dc < -(nax / 2)) dc += nax;
-    }
-    return (float)dc * ce + (ob - oa);
 }
 
 // displacement b - a and its square, all FP32

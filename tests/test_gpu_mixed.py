@@ -18,6 +18,11 @@ CASES = {
     "random": lambda: inputs.random_periodic(3001, seed=4, h_lo=0.06, h_hi=0.09),
     "blob": lambda: inputs.gaussian_blob(20000, seed=3, seed_v=33),
     "patch": lambda: inputs.square_patch(14),
+    # small periodic boxes: 4 cells per axis, so pairs within reach sit at a
+    # cell difference of half the axis (the minimum-image tie of the FP32
+    # displacement, taken by the sign of the offset difference)
+    "lattice7": lambda: inputs.lattice(7, seed=1, sigma_v=0.01),
+    "random400": lambda: inputs.random_periodic(400, seed=6, h_lo=0.15, h_hi=0.2),
 }
 
 
