@@ -274,3 +274,108 @@ def test_rollout_checkpoint_interval_invariant():
     grads = [_gpu_rollout_grad(w, a, target, 4, ckpt)[1] for ckpt in (1, 3, 4)]
     for g in grads[1:]:
         assert np.array_equal(g.view(np.uint64), grads[0].view(np.uint64))
+
+
+def _frozen_rollout_density(cfg, w, a0, v0, hs, dts, h_fin):
+    """rho (by id) at the end of the rollout with its structure frozen: step s
+    runs the stage entry points with h = hs[s] and dt = dts[s] (newton_iters = 0
+    in cfg), and the final density is evaluated at h_fin."""
+    arr = dict(a0)
+    for k, col in (("vx", 0), ("vy", 1), ("vz", 2)):
+        arr[k] = v0[:, col].copy()
+        arr["vh" + k[1]] = v0[:, col].copy()
+    r = Run(w, cfg, arr)
+    dt_m1 = 0.0
+    for s in range(len(dts)):
+        r.parts["h"] = torch.from_numpy(hs[s][r.ids()])
+        _frozen_step(cfg, r, dts[s], dt_m1)
+        dt_m1 = dts[s]
+    r.parts["h"] = torch.from_numpy(h_fin[r.ids()])
+    sph.build_cells(cfg, r.parts, r.ws)
+    sph.find_neighbors(cfg, r.parts, r.ws)
+    sph.density(cfg, r.parts, r.ws)
+    assert r.status() == (0, 0)
+    return r.by_id("rho")
+
+
+# The C5 differences (v0 + eps d, d of RMS 0.01 or one component of 0.01).
+# The AV switch (viscosity only where v_ab . x_ab < 0) is a kink of the step map:
+# the adjoint follows the recorded branch, while a central difference straddles
+# the switch for O(eps * pairs * steps) pairs, each an O(eps) error.  With the
+# viscosity off the map is smooth, and the differences converge as eps^2 down to
+# the rounding floor (eps = 1e-3 random, 1e-2 one component: 2e-8 .. 3e-7 in
+# a sweep of eps from 1e-2 to 1e-7); that case carries the 1e-6 bar, with two
+# step sizes Richardson-combined to remove the O(eps^2) term.  With the viscosity
+# of the benchmark (alpha = 1) the same sweep leaves 1e-6 .. 9e-4 at every step
+# size, scattered by the straddled switches, so that case is a plain central
+# difference held to 1e-2; its adjoint is pinned at 1e-12 against the oracle's
+# gradient on the small rollouts above.
+C5_CASES = {0.0: (1e-3, 1e-2, 1e-6, True), 1.0: (1e-6, 1e-4, 1e-2, False)}
+
+
+@pytest.mark.parametrize("alpha", sorted(C5_CASES))
+def test_rollout_c5_finite_differences(alpha):
+    """The 64^3 lattice rollout as benchmarked: 20 steps, a checkpoint every 5,
+    loss 1/2 |rho_20 - rho*|^2, gradient with respect to v0.  Checked against
+    central differences of the GPU's own frozen-structure rollout (h and dt of
+    every step as recorded) in 3 random directions of RMS 0.01 and 10 single
+    components of size 0.01.  The loss difference is formed as
+    sum (rho+ - rho-)((rho+ + rho-)/2 - rho*), which has no cancellation of the
+    loss itself."""
+    eps_dir, eps_comp, bar, richardson = C5_CASES[alpha]
+    w = inputs.c5_lattice()
+    n = w.n
+    target = inputs.c5_target_density(n)
+    cfg, _ = configs(w, alpha_av=alpha)
+    r = Run(w, cfg)
+    sph.initialise(cfg, r.parts, r.ws, r.g)
+    a0 = {k: r.by_id(k) for k in ("x", "y", "z", "h", "m", "u")}
+    a0["id"] = np.arange(n)
+    v0 = np.stack([w.arrays["vx"], w.arrays["vy"], w.arrays["vz"]], 1)
+    # gradient through the checkpointed rollout
+    ro = sph.Rollout(cfg, r.parts, r.g, r.ws, steps=20, ckpt=5)
+    v0_t = torch.tensor(v0, device="cuda", requires_grad=True)
+    rho = sph.DensityRollout.apply(v0_t, ro)
+    L = 0.5 * ((rho - torch.tensor(target, device="cuda")) ** 2).sum()
+    L.backward()
+    assert r.status() == (0, 0)
+    grad = v0_t.grad.cpu().numpy()
+    rho_ad = rho.detach().cpu().numpy()
+    # the structure of every step, recorded on a plain forward from the same state
+    sph.restore(r.parts, r.g, ro.initial)
+    hs, dts = [], []
+    for s in range(20):
+        sph.step(cfg, r.parts, r.g, r.ws)
+        hs.append(r.by_id("h"))
+        dts.append(float(r.g.t[0].item()))
+    sph.density_eval(cfg, r.parts, r.ws)
+    assert np.array_equal(r.by_id("rho"), rho_ad)     # the rollout's own forward
+    h_fin = r.by_id("h")
+    fz = cfg.replace(newton_iters=0)
+    rho_fz = _frozen_rollout_density(fz, w, a0, v0, hs, dts, h_fin)
+    assert rel_err(rho_fz, rho_ad) < 1e-13            # frozen replay = free forward
+
+    def dL(d, eps):
+        rp = _frozen_rollout_density(fz, w, a0, v0 + eps * d, hs, dts, h_fin)
+        rm = _frozen_rollout_density(fz, w, a0, v0 - eps * d, hs, dts, h_fin)
+        return float(np.sum((rp - rm) * (0.5 * (rp + rm) - target))) / (2 * eps)
+
+    rng = np.random.default_rng(57)
+    dirs = [(rng.normal(0.0, 0.01, (n, 3)), eps_dir) for _ in range(3)]
+    # single components drawn among those whose derivative is at least the
+    # median one: the differences carry an absolute rounding floor of ~1e-12
+    # after 20 steps, which a relative bar cannot resolve near a zero derivative
+    big = np.flatnonzero(np.abs(grad).ravel() >= np.median(np.abs(grad)))
+    for c in rng.choice(big, 10, replace=False):
+        d = np.zeros(3 * n)
+        d[c] = 0.01
+        dirs.append((d.reshape(n, 3), eps_comp))
+    worst = 0.0
+    for d, eps in dirs:
+        ad = float(np.sum(grad * d))
+        fd = (4.0 * dL(d, eps / 2) - dL(d, eps)) / 3.0 if richardson else dL(d, eps)
+        err = abs(fd - ad) / abs(ad)
+        worst = max(worst, err)
+        print(f"c5 alpha {alpha} fd {fd:.12e} adjoint {ad:.12e} rel {err:.1e}")
+        assert err <= bar, (fd, ad)
+    print(f"c5 alpha {alpha} worst {worst:.1e}")

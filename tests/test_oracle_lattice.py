@@ -100,6 +100,22 @@ def test_shell_counts(ora, s, count):
     assert np.all(nc == count) and np.all(ns == count)
 
 
+def test_support_boundary_is_strict(ora):
+    """Support is v < 2 (eq. 6): on the 8^3 lattice with h = 1/8 exactly, the
+    axis neighbours at 2 spacings sit on r = 2h with every quantity exact and are
+    excluded (26 = the shells r^2 <= 3 spacings^2); one ulp more of h takes
+    them in (32)."""
+    w = inputs.lattice(8, sigma_v=0.0)
+    cfg = oracle_config(w.params)
+    a = w.arrays
+    h = np.full(a["x"].size, 0.125)
+    nc, ns, _, _ = ora.neighbors(cfg, a["x"], a["y"], a["z"], h, with_lists=False)
+    assert np.all(nc == 26) and np.all(ns == 26)
+    h1 = np.nextafter(h, 1.0)
+    nc, ns, _, _ = ora.neighbors(cfg, a["x"], a["y"], a["z"], h1, with_lists=False)
+    assert np.all(nc == 32) and np.all(ns == 32)
+
+
 def test_neighbor_sets_brute_force_numpy(ora):
     """Gather and symmetric sets against a direct numpy evaluation (random h)."""
     w = inputs.random_periodic(300, seed=3, h_lo=0.08, h_hi=0.15)
