@@ -7,8 +7,9 @@
  * ---------------------------------------
  * - Pointers are DEVICE pointers unless a comment says (host).  Every array is
  *   caller-owned, length cfg->n, stride 1, FP64 unless stated (structure of
- *   arrays).  The library allocates nothing, frees nothing and keeps no global
- *   state; all scratch lives in the caller's workspace `ws`.
+ *   arrays).  The library allocates nothing and frees nothing; all scratch
+ *   lives in the caller's workspace `ws`, except for sph_step_static, whose
+ *   scratch is a fixed device array of the library (the only global state).
  * - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
  *   only enqueues work on it and returns; results are ready when the stream is.
  *   Two workspaces may be used concurrently on two streams.
@@ -204,6 +205,25 @@ sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, voi
 #define SPH_STEP_PHASES 8
 sph_status sph_step_marked(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
                            sph_stream stream, void* const* events, int32_t nevents);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sph_step
+ * without a caller workspace.  Its scratch is a fixed device array of
+ * SPH_STATIC_SCRATCH_BYTES held by the library on each GPU it runs on until
+ * the process ends; the call allocates nothing and frees nothing.  The caller
+ * still passes the particles and globals as for sph_step, on the current
+ * device (the stream must belong to it).
+ * Limit: configurations whose sph_workspace_bytes exceeds
+ * SPH_STATIC_SCRATCH_BYTES return SPH_E_WORKSPACE before anything is enqueued
+ * (64 MiB: about 26,000 particles at ng_max = 160).
+ * err_out: device pointer to one uint32 that receives this call's device error
+ * word (SPH_ERRBIT_* bits) when the stream reaches the end of the step, or
+ * NULL.  Each call starts from a cleared word.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two streams, two threads) race and give undefined results. */
+#define SPH_STATIC_SCRATCH_BYTES (64u << 20)
+sph_status sph_step_static(const sph_config* cfg, sph_particles* p, sph_globals* g,
+                           uint32_t* err_out, sph_stream stream);
 
 /* ------------------------------------------------------------------------
  * Reverse mode (adjoint) of one step.  The map differentiated is the step of

@@ -1,7 +1,11 @@
 // sph_api.hip -- the C ABI of libsph: argument validation, workspace carve-up and
-// launch sequencing on the caller's stream.  No allocation, no global state.
+// launch sequencing on the caller's stream.  No allocation; the only global
+// state is the fixed device scratch of sph_step_static and its per-device
+// address.
 #include <math.h>
 #include <string.h>
+
+#include <mutex>
 
 #include "sph_common.h"
 
@@ -424,6 +428,68 @@ sph_status sph_step_marked(const sph_config* cfg, sph_particles* p, sph_globals*
     hipError_t e = launch_integrate(c.P, c.W, p, g, c.s);
     mk.at(8, c.s);
     return hip_status(e);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free step
+// sph_step_static runs sph_step with its workspace in this fixed device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// In host code `scratch` names a host-side stand-in, not device memory: every
+// host use goes through the address hipGetSymbolAddress returns for the
+// current device, taken once per device on the first call there.
+namespace {
+
+static_assert(SPH_STATIC_SCRATCH_BYTES % 256 == 0, "scratch size must keep 256-byte alignment");
+__device__ __align__(256) unsigned char scratch[SPH_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// device address of this device's scratch, or nullptr
+void* static_scratch()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void* ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = ptr;
+    });
+    return g_scratch_err[dev] == hipSuccess ? g_scratch_ptr[dev] : nullptr;
+}
+
+__global__ void k_copy_err(const Domain* __restrict__ dom, uint32_t* __restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = dom->err;
+}
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_step_static(const sph_config* cfg, sph_particles* p, sph_globals* g,
+                           uint32_t* err_out, sph_stream stream)
+{
+    if (!config_ok(cfg)) return SPH_E_ARG;
+    if (make_layout(cfg->n, cfg->ng_max).total > (size_t)SPH_STATIC_SCRATCH_BYTES)
+        return SPH_E_WORKSPACE;
+    if (!step_args_ok(cfg, p, g)) return SPH_E_ARG;
+    void* ws = static_scratch();
+    if (!ws) return SPH_E_HIP;
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    // the array keeps the last call's contents: the header record (error word,
+    // flags, cached domain) starts from zero; everything else a step reads it
+    // writes first
+    if (launch_clear_domain(c.W, c.s) != hipSuccess) return SPH_E_HIP;
+    if ((st = step_rates(c, p, g))) return st;
+    if (launch_integrate(c.P, c.W, p, g, c.s) != hipSuccess) return SPH_E_HIP;
+    if (err_out) k_copy_err<<<1, 64, 0, c.s>>>(c.W.dom, err_out);
+    return hip_status(hipGetLastError());
 }
 
 size_t sph_adjoint_workspace_bytes(const sph_config* cfg)

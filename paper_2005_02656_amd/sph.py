@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_WORKSPACE
                 7: "SPH_E_SINGULAR_TAU"}
 ERRBIT_NEIGHBOR_OVERFLOW, ERRBIT_CELL_RANGE, ERRBIT_NONFINITE, ERRBIT_SINGULAR_TAU = 1, 2, 4, 8
 SHORT_REACH = 1.03   # SPH_SHORT_REACH: the fused step's short candidate reach lambda
+STATIC_SCRATCH_BYTES = 64 << 20   # SPH_STATIC_SCRATCH_BYTES: sph_step_static's scratch
 FP64, MIXED = 0, 1
 
 STATE_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",
@@ -144,6 +145,7 @@ _SIGS = {
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p]),
     "sph_status_string": (C.c_char_p, [C.c_int]),
+    "sph_step_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -302,6 +304,19 @@ def step(cfg: Config, parts: Particles, g: Globals, ws: Workspace, stream=None):
 
 STEP_PHASES = ("build_cells", "candidates", "newton_h", "lists", "density", "iad",
                "momentum_energy", "integrate")
+
+
+def step_static(cfg: Config, parts: Particles, g: Globals, err: torch.Tensor = None,
+                stream=None):
+    """Enqueues sph_step_static: sph_step with the library's fixed device scratch
+    instead of a workspace (no allocation).  err: optional int32 device tensor of
+    one element that receives the step's device error bits."""
+    if err is not None and (err.dtype != torch.int32 or err.numel() != 1):
+        raise ValueError("err must be a one-element int32 tensor")
+    ps = parts.c()
+    _check(lib().sph_step_static(C.byref(cfg.c()), C.byref(ps), g.ptr,
+                                 C.c_void_p(err.data_ptr()) if err is not None else None,
+                                 _stream(stream)), "sph_step_static")
 
 
 class StepMarks:

@@ -36,6 +36,8 @@ def test_constants_match_the_header(sph):
     src = open(os.path.join(ROOT, "include", "sph.h")).read()
     defs = dict(re.findall(r"#define (SPH_\w+) (.+)", src))
     assert float(defs["SPH_SHORT_REACH"]) == sph.SHORT_REACH
+    m = re.fullmatch(r"\((\d+)u << (\d+)\)", defs["SPH_STATIC_SCRATCH_BYTES"].strip())
+    assert int(m.group(1)) << int(m.group(2)) == sph.STATIC_SCRATCH_BYTES
     assert int(defs["SPH_STEP_PHASES"]) == len(sph.STEP_PHASES)
     shift = lambda d: 1 << int(re.fullmatch(r"\(1u << (\d+)\)", d.strip()).group(1))
     bits = {k: shift(defs["SPH_ERRBIT_" + k]) for k in
@@ -69,6 +71,23 @@ def test_argument_errors_are_synchronous(sph):
     assert L.sph_build_cells(C.byref(cfg.c()), C.byref(parts), None, None) == 3
     assert L.sph_density(C.byref(cfg.c()), C.byref(parts), C.c_void_p(256), None) == 1
     assert L.sph_timestep(C.byref(cfg.c()), None, C.c_void_p(256), None) == 1
+
+
+def test_static_step_rejects_before_enqueuing(sph):
+    """sph_step_static validates on the host: bad config or particles give
+    SPH_E_ARG and a workspace larger than the fixed scratch SPH_E_WORKSPACE,
+    before any device call."""
+    L = sph.lib()
+    parts = sph._Particles()
+    g = C.c_void_p(256)
+    assert L.sph_step_static(None, C.byref(parts), g, None, None) == 1
+    assert L.sph_step_static(C.byref(sph.Config(n=0).c()), C.byref(parts), g, None, None) == 1
+    big = sph.Config(n=200_000)
+    assert L.sph_workspace_bytes(C.byref(big.c())) > sph.STATIC_SCRATCH_BYTES
+    assert L.sph_step_static(C.byref(big.c()), C.byref(parts), g, None, None) == 3
+    small = sph.Config(n=8000)
+    assert L.sph_workspace_bytes(C.byref(small.c())) <= sph.STATIC_SCRATCH_BYTES
+    assert L.sph_step_static(C.byref(small.c()), C.byref(parts), g, None, None) == 1
 
 
 def test_status_strings(sph):
