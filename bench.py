@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
                     [--precision fp64|mixed] [--no-cpu-baseline] [--no-mixed]
-                    [--no-adjoint]
+                    [--no-adjoint] [--oracle-points]
 
 A step is one sph_step (Morton sort into cells, Newton h update, neighbour
 search, density, IAD, momentum/energy with AV, global dt, integration and
@@ -41,56 +41,41 @@ WORKLOADS = {
            "c4_square_patch"),
 }
 
-# Algorithmic work of each phase of sph_step (the per-unit figures are derived in
-# the design notes).  Flops are FP64 operations (an fma counts 2) of the
-# arithmetic the phase needs per unit: neighbour pair for the pair passes
-# (k_g gather pairs, k_s symmetric pairs per particle), candidate pair for the
-# Newton iterations.  Bytes are HBM bytes with every datum read or written once.
-FLOPS_PER_PAIR = {
-    # r^2 (8), t (1), sinc and x sinc' polynomials (11 + 10 terms: 39), s^n, S,
-    # v dS/dv (6), the two sums (2)
-    "newton_h": 56,
-    # as Newton, with mass-weighted sums (6); in the fused step the list filter
-    # does this work for the gather pairs
-    "density": 60,
-    "lists": 60,
-    # r^2, t, sinc polynomial and s^n (33), V W (2), six d_i d_j products summed (15)
-    "iad": 50,
-    # r^2, W(h_a) and W(h_b) (55), C_a d and C_b d scaled by W (36), v_ab, x.v, AV
-    # (16), g, the pressure terms and a (30), e1 and e2 (13)
-    "momentum_energy": 160,
-}
+# Algorithmic work of each phase of sph_step: what the method itself must do,
+# independent of how this implementation does it.  Flops are FP64 operations (an
+# fma counts 2) of the SPH arithmetic per pair, with the kernel S_n evaluated as
+# an even polynomial in v^2 (no sqrt, sin or pow per pair): Newton ~30 per
+# candidate pair and iteration, density and Omega ~45 and IAD ~35 per gather
+# pair, momentum, energy and viscosity ~110 per symmetric pair.  The candidate
+# distance tests of the search are not counted (their number depends on the cell
+# structure, not on the method).
+FLOPS_PER_PAIR = {"newton_h": 30, "lists": 45, "density": 45, "iad": 35,
+                  "momentum_energy": 110}
 
 
 def bytes_per_particle(phase, k_g, k_s, wc, k_c=0.0, iters=2, fused=True, urec=False):
-    """Algorithmic HBM bytes per particle of one phase of sph_step.  urec: the
-    momentum records take m and c from slot 0 (equal masses and sound speeds),
-    112 bytes instead of 144."""
-    rec = 112 if urec else 144
+    """Algorithmic HBM bytes per particle of one phase of sph_step: every FP64
+    state field and int32 list entry the phase must read or write, once.  The
+    neighbours' fields are taken as served from the caches (the measured
+    counter traffic against this figure is the cache amplification).  Per kernel:
+    bbox 32, keys 36, sort 24 (one read and one write of key and index), permute
+    228 (ideal gas) / 260 (weakly compressible), cells 8, Newton 72 (x y z h per
+    iteration + h out), neighbours 36 (x y z h in, counts out), density 80 / 96,
+    IAD 96, momentum/energy 176, integrate 184, and the neighbour list written
+    once and read by density, IAD and momentum (4 k_s each).  The step total is
+    972 + 16 k_s (ideal gas) or 1,020 + 16 k_s (weakly compressible)."""
+    lst = 4.0 * k_s
     return {
-        # bbox (x y z h), keys, 8 radix passes over 8-byte keys and 4-byte indices,
-        # permutation of the state (15 fields with the weakly compressible EOS,
-        # else 13, plus the id), packed positions (32 B) and FP32 walk records
-        # (16 B), cell table fill
-        "build_cells": 32 + 12 + 8 * 24 + (16 if wc else 14) * 16 + 32 + 16 + 8,
-        # p4 of the target and the FP32 walk records read, candidate list and
-        # count written (k_c candidates per particle)
-        "candidates": 32 + 16 + 4 + 4 * k_c,
-        # p4 read, candidate list read once per iteration, h written
-        "newton_h": 32 + 8 + 4 * k_c * iters,
-        # p4 repack, candidates read, counts and the filtered list written, and
-        # (fused step) the density's own fields: m u (p_ref rho_ref) in, 4 out
-        "lists": 64 + 4 + 4 * k_c + 8 + 4 * k_s + ((64 if wc else 48) if fused else 0),
-        # separate density pass (stage path): p4 m u (p_ref rho_ref), list, 4 out
-        "density": 0 if fused else (100 if wc else 84) + 4 * k_g,
-        # volume pass: m rho p4 in, m/rho and {x y z m/rho} out; the m and c
-        # uniformity check; IAD pass: p4 of the target, {x y z m/rho} records,
-        # count and list, the record's other sources (m rho omega p c v), C and
-        # the momentum records out
-        "iad": (16 + 32 + 8 + 32) + 16 + 32 + 32 + 4 + 4 * k_g + 64 + 48 + rec,
-        # the target's record, its C rho omega p h, u, counts, list, 4 out
-        "momentum_energy": rec + 48 + 24 + 8 + 8 + 8 + 4 * k_s + 32,
-        "integrate": 13 * 8 + 4 * 8 + 11 * 8,          # state + rates in, state out
+        "build_cells": 32 + 36 + 24 + (260 if wc else 228) + 8,
+        "candidates": 0.0,
+        "newton_h": 32 * iters + 8,
+        # neighbour search (write of the list) and, in the fused step, the
+        # density formed while the list is filtered (its list read counted here)
+        "lists": 36 + lst + ((96 if wc else 80) + lst if fused else 0.0),
+        "density": 0.0 if fused else (96 if wc else 80) + lst,
+        "iad": 96 + lst,
+        "momentum_energy": 176 + lst,
+        "integrate": 184,
     }[phase]
 
 
@@ -108,6 +93,8 @@ def parse():
                     help="skip the adjoint/forward timing of the 64^3 rollout")
     ap.add_argument("--cpu-sample-side", type=int, default=48,
                     help="side of the square-patch lattice the oracle steps on")
+    ap.add_argument("--oracle-points", action="store_true",
+                    help="also time the oracle on the 20^3 and 32^3 lattices, all cores and one")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (scales HBM counters)")
     return ap.parse_args()
@@ -148,9 +135,11 @@ def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload, fused, urec=False):
     kern = PHASE_KERNEL[dom]
     if dom == "momentum_energy" and urec:
         kern = "k_momentum_energy_u"   # the kernel of the 112-byte records
-    res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom],
-           "traffic": traffic_from_profile(kern, workload)}
-    pairs = {"newton_h": iters * k_c * n, "density": k_g * n, "lists": k_g * n,
+    traffic = traffic_from_profile(kern, workload)
+    res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom], "traffic": traffic,
+           "algorithmic_bytes": by * n,
+           "traffic_over_algorithmic": traffic / (by * n) if traffic else None}
+    pairs = {"newton_h": iters * k_s * n, "density": k_g * n, "lists": k_g * n,
              "iad": k_g * n, "momentum_energy": k_s * n}
     if dom in FLOPS_PER_PAIR and pairs.get(dom):
         fl = FLOPS_PER_PAIR[dom] * pairs[dom]
@@ -226,6 +215,32 @@ def cpu_baseline(side):
                       f"smaller); {t:.1f} s"}
 
 
+def oracle_points():
+    """The oracle's throughput on the 20^3 lattice (8,000 particles) and on a 32^3
+    lattice (32,768), one full step each from the generator's state, on all host
+    cores and on one (the brute-force cost does not depend on h)."""
+    import oracle
+    from paper_2005_02656_amd import inputs
+    keys = set(oracle.Config.__dataclass_fields__)
+    allc = oracle.num_threads()
+    pts = []
+    for side in (20, 32):
+        w = inputs.lattice(side, seed=1, sigma_v=0.01)
+        ocfg = oracle.Config(**{k: v for k, v in w.params.items() if k in keys})
+        st = {k: np.array(v, copy=True) for k, v in w.arrays.items()}
+        st.update(vhx=st["vx"].copy(), vhy=st["vy"].copy(), vhz=st["vz"].copy(),
+                  du_m1=np.zeros(w.n))
+        for cores in (allc, 1):
+            oracle.set_num_threads(cores)
+            t0 = time.perf_counter()
+            oracle.step(ocfg, st, {"dt_m1": 0.0, "t": 0.0})
+            t = time.perf_counter() - t0
+            pts.append({"workload": f"lattice {side}^3 = {w.n} particles, one step",
+                        "cores": cores, "seconds": t, "value": w.n / t})
+    oracle.set_num_threads(allc)
+    return pts
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -273,8 +288,11 @@ def main():
     if st:
         raise RuntimeError(f"timed steps raised {sph.status_string(st)} (bits {bits})")
     phases = {k: 0.0 for k in sph.STEP_PHASES}
+    per_step = []
     for mk in marks:
-        for k, v in mk.phase_ms().items():
+        pm = mk.phase_ms()
+        per_step.append(sum(pm.values()))
+        for k, v in pm.items():
             phases[k] += v / args.steps
     log(f"[bench] {args.steps} timed steps: {ms:.3f} ms/step; phases "
         + " ".join(f"{k}={v:.2f}" for k, v in phases.items()))
@@ -293,7 +311,8 @@ def main():
         "value": n / (ms * 1e-3),
         "unit": "particle-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": ms, "ms_per_step_median": float(np.median(per_step)),
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == sph.FP64 else "f32-pair/f64-accumulate",
         "data": "synthetic",
@@ -313,7 +332,7 @@ def main():
     step_bytes = sum(bytes_per_particle(k, k_g, k_s, wc, k_c, cfg.newton_iters, fused, urec)
                      for k in phases) * n
     out["step_hbm_frac"] = step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
-    step_flops = n * (FLOPS_PER_PAIR["newton_h"] * cfg.newton_iters * k_c
+    step_flops = n * (FLOPS_PER_PAIR["newton_h"] * cfg.newton_iters * k_s
                       + FLOPS_PER_PAIR["lists"] * k_g + FLOPS_PER_PAIR["iad"] * k_g
                       + FLOPS_PER_PAIR["momentum_energy"] * k_s)
     out["step_fp64_valu_frac"] = step_flops / (ms * 1e-3) / (FP64_VALU_PEAK_TFLOPS * 1e12)
@@ -362,6 +381,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_side)
+        if args.oracle_points:
+            out["cpu_baseline"]["points"] = oracle_points()
     print(json.dumps(out), flush=True)
 
 

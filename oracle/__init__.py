@@ -328,3 +328,8 @@ def step(cfg, st, gl):
 def num_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Sets the OpenMP threads of the oracle's loops (for timing on k cores)."""
+    lib().ora_set_num_threads(C.c_int(int(k)))

@@ -637,6 +637,8 @@ void ora_sort_keys(int64_t n, const uint64_t* keys, int64_t* perm)
 #ifdef _OPENMP
 #include <omp.h>
 int ora_num_threads(void) { return omp_get_max_threads(); }
+void ora_set_num_threads(int k) { omp_set_num_threads(k > 0 ? k : 1); }
 #else
 int ora_num_threads(void) { return 1; }
+void ora_set_num_threads(int k) { (void)k; }
 #endif

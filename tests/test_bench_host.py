@@ -22,21 +22,27 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_byte_model_per_phase():
+    """The algorithmic model of the step: 1,020 + 16 k_s bytes per particle
+    under the weakly compressible EOS and 972 + 16 k_s with the ideal gas, split
+    over the phases as the kernels of the method read and write them."""
     k_g, k_s, k_c = 91.7, 91.8, 121.5
+    for wc, base in ((True, 1020), (False, 972)):
+        tot = sum(bench.bytes_per_particle(ph, k_g, k_s, wc, k_c, 2)
+                  for ph in bench.PHASE_KERNEL)
+        assert tot == pytest.approx(base + 16 * k_s)
+        unfused = sum(bench.bytes_per_particle(ph, k_g, k_s, wc, k_c, 2, fused=False)
+                      for ph in bench.PHASE_KERNEL)
+        assert unfused == pytest.approx(tot)
     bpp = lambda ph, **kw: bench.bytes_per_particle(ph, k_g, k_s, True, k_c, 2, **kw)
-    # momentum: the target's 144-byte record and unfolded C rho omega p h, u, the
-    # two counts, the list, four outputs; 112-byte records with equal m and c
-    assert bpp("momentum_energy") == pytest.approx(144 + 80 + 8 + 8 + 4 * k_s + 32)
-    assert bpp("momentum_energy") - bpp("momentum_energy", urec=True) == 32
-    assert bpp("iad") - bpp("iad", urec=True) == 32
-    # the candidate lists are read once per Newton iteration
-    assert bpp("newton_h") == pytest.approx(40 + 8 * k_c)
+    # momentum: 12 FP64 fields and 6 C in, 4 out, the list read once
+    assert bpp("momentum_energy") == pytest.approx(176 + 4 * k_s)
+    # the implementation's record layout does not change what the method moves
+    assert bpp("momentum_energy", urec=True) == bpp("momentum_energy")
+    # Newton: x y z h per iteration and h out
+    assert bpp("newton_h") == pytest.approx(72)
     # with the fused step the density is formed in the list filter
     assert bpp("density") == 0
-    assert bpp("density", fused=False) > 0
-    assert bpp("lists") - bpp("lists", fused=False) == 64   # m u p_ref rho_ref in, 4 out
-    for ph in bench.PHASE_KERNEL:
-        assert bench.bytes_per_particle(ph, k_g, k_s, False, k_c, 2) > 0 or ph == "density"
+    assert bpp("density", fused=False) == pytest.approx(96 + 4 * k_s)
 
 
 def test_roofline_reports_the_binding_ceiling():
