@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
                     [--precision fp64|mixed] [--no-cpu-baseline] [--no-mixed]
-                    [--no-adjoint] [--oracle-points]
+                    [--no-adjoint] [--no-table] [--oracle-points]
 
 A step is one sph_step (Morton sort into cells, Newton h update, neighbour
 search, density, IAD, momentum/energy with AV, global dt, integration and
@@ -11,7 +11,8 @@ The set-up (initial conditions, upload, the Newton initialisation of h and the
 reference density) is untimed.  The timed steps run through sph_step_marked
 (the same launches plus HIP events between phases) so the per-phase times and
 the roofline of the longest phase come from the timed steps themselves.  Then,
-unless switched off: the same workload in mixed precision, the adjoint/forward
+unless switched off: the same workload in mixed precision, the kernel
+lookup-table variant (FP64 and mixed), the adjoint/forward
 time of the 64^3 rollout, and the FP64 oracle timed on the host on a bounded
 sample.  Prints ONE JSON line.
 """
@@ -89,6 +90,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision timing of the same workload")
+    ap.add_argument("--no-table", action="store_true",
+                    help="skip the timing of the kernel lookup-table variant")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward timing of the 64^3 rollout")
     ap.add_argument("--cpu-sample-side", type=int, default=48,
@@ -359,6 +362,30 @@ def main():
                         "phase_ms": {k: round(v, 4) for k, v in mph.items()},
                         "note": "same workload and state, FP32 pair terms with FP64 sums"}
         log(f"[bench] mixed precision: {mms:.3f} ms/step")
+    if not args.no_table:
+        # the kernel lookup table of section 4.5 (20,000 values, linear
+        # interpolation in v) in place of the fitted polynomials, same state
+        out["kernel_table"] = {"entries": sph.KERNEL_TABLE_PAPER}
+        for name, pr in (("fp64", sph.FP64), ("mixed", sph.MIXED)):
+            tcfg = cfg.replace(precision=pr, kernel_table=sph.KERNEL_TABLE_PAPER)
+            sph.step(tcfg, parts, g, ws)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(args.steps):
+                sph.step_marked(tcfg, parts, g, ws, marks[i])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tms = e0.elapsed_time(e1) / args.steps
+            tph = {k: 0.0 for k in sph.STEP_PHASES}
+            for mk in marks:
+                for k, v in mk.phase_ms().items():
+                    tph[k] += v / args.steps
+            st, bits = sph.status_sync(ws)
+            if st:
+                raise RuntimeError(f"table steps raised {sph.status_string(st)} (bits {bits})")
+            out["kernel_table"][name] = {"ms_per_step": tms,
+                                         "phase_ms": {k: round(v, 4) for k, v in tph.items()}}
+        log(f"[bench] kernel table: {out['kernel_table']}")
     del parts, ws
     torch.cuda.empty_cache()
 

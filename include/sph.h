@@ -83,8 +83,18 @@ typedef struct {
     double  acc_dt;         /* acceleration criterion acc_dt * sqrt(h/|a|); 0 = off */
     double  energy_dt;      /* energy criterion energy_dt * |u|/|du|; 0 = off */
     int32_t precision;      /* sph_precision */
-    int32_t reserved;       /* must be 0 */
+    int32_t kernel_table;   /* 0: S_n evaluated directly (fitted even polynomials in
+                             *    v^2, FP64 to 1e-15); N in 2..SPH_KERNEL_TABLE_MAX:
+                             *    S_n and dS_n/dv read from tables of N values at
+                             *    v_i = 2i/(N-1) and interpolated linearly in v
+                             *    (section 4.5 uses N = 20,000).  Applies to every
+                             *    kernel evaluation of the forward step, in both
+                             *    precisions; the reverse mode needs 0. */
 } sph_config;
+
+/* largest kernel_table; the tables live in the workspace, which always
+ * reserves room for the largest (48 bytes per entry, 3 MiB) */
+#define SPH_KERNEL_TABLE_MAX 65536
 
 /* Particle arrays (device, caller-owned).  State arrays are permuted in place by
  * sph_build_cells; output arrays are written by the stage that names them. */

@@ -46,6 +46,7 @@ class Config:
     dt_growth: float = 1.1
     acc_dt: float = 0.2
     energy_dt: float = 0.2
+    kernel_table: int = 0  # 0: exact S_n; N > 1: the N-value table of section 4.5
 
     def replace(self, **kw) -> "Config":
         return dataclasses.replace(self, **kw)
@@ -68,6 +69,7 @@ class _CConfig(C.Structure):
         ("dt_growth", C.c_double),
         ("acc_dt", C.c_double),
         ("energy_dt", C.c_double),
+        ("kernel_table", C.c_int32),
     ]
 
 
@@ -88,6 +90,7 @@ def _cc(cfg: Config) -> _CConfig:
     c.dt_growth = cfg.dt_growth
     c.acc_dt = cfg.acc_dt
     c.energy_dt = cfg.energy_dt
+    c.kernel_table = int(cfg.kernel_table)
     return c
 
 
@@ -107,6 +110,9 @@ def lib():
         for f in ("ora_W", "ora_dWdh"):
             getattr(_lib, f).restype = d
             getattr(_lib, f).argtypes = [d, d, d, d]
+        for f in ("ora_S_cfg", "ora_dSdv_cfg"):
+            getattr(_lib, f).restype = d
+            getattr(_lib, f).argtypes = [vp, d]
         _lib.ora_timestep.restype = d
         _lib.ora_timestep.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, d]
     return _lib
@@ -141,6 +147,15 @@ def S(v: float, n: float) -> float:
 
 def dSdv(v: float, n: float) -> float:
     return lib().ora_dSdv(float(v), float(n))
+
+
+def S_cfg(cfg, v: float) -> float:
+    """S_n(pi v/2) as cfg evaluates it (exactly, or from its lookup table)."""
+    return lib().ora_S_cfg(C.byref(_cc(cfg)), float(v))
+
+
+def dSdv_cfg(cfg, v: float) -> float:
+    return lib().ora_dSdv_cfg(C.byref(_cc(cfg)), float(v))
 
 
 def W(r2: float, h: float, n: float, b: float) -> float:

@@ -43,6 +43,7 @@ typedef struct {
     double  courant, dt_growth;
     double  acc_dt;        /* coefficient of the acceleration criterion, 0 = off */
     double  energy_dt;     /* coefficient of the energy criterion, 0 = off */
+    int32_t kernel_table;  /* 0: S_n exact; N > 1: the N-value lookup table (section 4.5) */
 } ora_config;
 
 /* ------------------------------------------------------------------------ */
@@ -151,6 +152,56 @@ double ora_bn(double n)
     return 1.0 / (4.0 * ORA_PI * s);
 }
 
+/* Kernel lookup table (section 4.5): with N = kernel_table > 1 values at the
+ * nodes v_i = 2i/(N-1), S_n(v) and dS_n/dv are interpolated linearly in v
+ * between the exact values at the two nodes around v, (1 - f) y_i + f y_{i+1}
+ * with i = floor(v (N-1)/2) (clamped to the last interval) and f the fraction
+ * past node i.  With N = 0 they are evaluated exactly. */
+static double ora_table_lerp(const ora_config* cf, double v, int deriv)
+{
+    const int64_t N = cf->kernel_table;
+    const double s = v * (0.5 * (double)(N - 1));
+    int64_t i = (int64_t)s;
+    if (i > N - 2) i = N - 2;
+    const double f = s - (double)i;
+    const double v0 = 2.0 * (double)i / (double)(N - 1);
+    const double v1 = 2.0 * (double)(i + 1) / (double)(N - 1);
+    const double y0 = deriv ? ora_dSdv(v0, cf->sinc_n) : ora_S(v0, cf->sinc_n);
+    const double y1 = deriv ? ora_dSdv(v1, cf->sinc_n) : ora_S(v1, cf->sinc_n);
+    return (1.0 - f) * y0 + f * y1;
+}
+
+static double ora_Sk(const ora_config* cf, double v)
+{
+    return cf->kernel_table > 1 ? ora_table_lerp(cf, v, 0) : ora_S(v, cf->sinc_n);
+}
+
+static double ora_dSk(const ora_config* cf, double v)
+{
+    return cf->kernel_table > 1 ? ora_table_lerp(cf, v, 1) : ora_dSdv(v, cf->sinc_n);
+}
+
+/* S_n and dS_n/dv as the configuration evaluates them, at one v (pins) */
+double ora_S_cfg(const ora_config* cf, double v) { return ora_Sk(cf, v); }
+double ora_dSdv_cfg(const ora_config* cf, double v) { return ora_dSk(cf, v); }
+
+/* W and dW/dh through the configured kernel evaluation */
+static double ora_Wc(const ora_config* cf, double r2, double h, double bn)
+{
+    double h2 = 2.0 * h;
+    if (!(r2 < h2 * h2)) return 0.0;
+    double v = sqrt(r2) / h;
+    return bn / (h * h * h) * ora_Sk(cf, v);
+}
+
+static double ora_dWdhc(const ora_config* cf, double r2, double h, double bn)
+{
+    double h2 = 2.0 * h;
+    if (!(r2 < h2 * h2)) return 0.0;
+    double v = sqrt(r2) / h;
+    return -bn / (h * h * h * h) * (3.0 * ora_Sk(cf, v) + v * ora_dSk(cf, v));
+}
+
 /* W(r, h) with support r^2 < (2h)^2; r2 is the squared distance */
 double ora_W(double r2, double h, double n, double bn)
 {
@@ -202,8 +253,8 @@ void ora_update_h(const ora_config* cf, int64_t n, const double* x, const double
                 double r2 = ora_disp(cf, x, y, z, a, b, d);
                 if (r2 < R2) {
                     double v = sqrt(r2) / h;
-                    sS += ora_S(v, cf->sinc_n);
-                    sV += v * ora_dSdv(v, cf->sinc_n);
+                    sS += ora_Sk(cf, v);
+                    sV += v * ora_dSk(cf, v);
                 }
             }
             double F = k3 * bn * sS - cf->n_target;
@@ -234,8 +285,8 @@ void ora_newton_terms(const ora_config* cf, int64_t n, const double* x, const do
             double r2 = ora_disp(cf, x, y, z, a, b, d);
             if (r2 < h2 * h2) {
                 double v = sqrt(r2) / ha;
-                sS += ora_S(v, cf->sinc_n);
-                sV += v * ora_dSdv(v, cf->sinc_n);
+                sS += ora_Sk(cf, v);
+                sV += v * ora_dSk(cf, v);
             }
         }
         F[a] = k3 * bn * sS - cf->n_target;
@@ -302,8 +353,8 @@ void ora_density(const ora_config* cf, int64_t n, const double* x, const double*
         for (int64_t b = 0; b < n; ++b) {
             double d[3];
             double r2 = ora_disp(cf, x, y, z, a, b, d);
-            sr += m[b] * ora_W(r2, ha, cf->sinc_n, bn);
-            sw += m[b] * ora_dWdh(r2, ha, cf->sinc_n, bn);
+            sr += m[b] * ora_Wc(cf, r2, ha, bn);
+            sw += m[b] * ora_dWdhc(cf, r2, ha, bn);
         }
         rho[a] = sr;
         omega[a] = 1.0 + ha / (3.0 * sr) * sw;
@@ -339,7 +390,7 @@ void ora_iad(const ora_config* cf, int64_t n, const double* x, const double* y,
             if (b == a) continue;
             double d[3];
             double r2 = ora_disp(cf, x, y, z, a, b, d);
-            double w = ora_W(r2, ha, cf->sinc_n, bn);
+            double w = ora_Wc(cf, r2, ha, bn);
             if (w == 0.0) continue;
             double s = m[b] / rho[b] * w;
             t11 += s * d[0] * d[0];
@@ -411,8 +462,8 @@ void ora_momentum_energy(const ora_config* cf, int64_t n, const double* x, const
             double hm2 = 2.0 * hm;
             if (!(r2 < hm2 * hm2)) continue;
             double r = sqrt(r2);
-            double wa = ora_W(r2, h[a], cf->sinc_n, bn);
-            double wb = ora_W(r2, h[b], cf->sinc_n, bn);
+            double wa = ora_Wc(cf, r2, h[a], bn);
+            double wb = ora_Wc(cf, r2, h[b], bn);
             double Cb[6] = {c11[b], c12[b], c13[b], c22[b], c23[b], c33[b]};
             double Aa[3], Ab[3];
             ora_cmul(Ca, d, wa, Aa);

@@ -55,6 +55,11 @@ Layout make_layout(int64_t n, int ng_max)
     L.posm = take(mixed_posm_bytes() * n);
     L.mf = take(sizeof(float) * n);
     L.mf2 = take(sizeof(float) * n);
+    // kernel tables, sized for the largest kernel_table whatever the config
+    L.tabS = take(sizeof(double2) * SPH_KERNEL_TABLE_MAX);
+    L.tabD = take(sizeof(double2) * SPH_KERNEL_TABLE_MAX);
+    L.tabSf = take(sizeof(float2) * SPH_KERNEL_TABLE_MAX);
+    L.tabDf = take(sizeof(float2) * SPH_KERNEL_TABLE_MAX);
     L.total = o;
     return L;
 }
@@ -87,6 +92,10 @@ Ws carve(void* ws, const Layout& L)
     W.pv = (PosV*)(b + L.pv);
     W.list = (int32_t*)(b + L.list);
     W.tmp = (double*)(b + L.list);
+    W.tabS = (double2*)(b + L.tabS);
+    W.tabD = (double2*)(b + L.tabD);
+    W.tabSf = (float2*)(b + L.tabSf);
+    W.tabDf = (float2*)(b + L.tabDf);
     return W;
 }
 
@@ -160,6 +169,8 @@ Params make_params(const sph_config* cfg, double bn, int lcap, int cand_cap)
     P.lcap = lcap;
     P.cand_cap = cand_cap;
     P.precision = cfg->precision;
+    P.tab_n = cfg->kernel_table;
+    P.tab_inv_dv = cfg->kernel_table > 1 ? 0.5 * (double)(cfg->kernel_table - 1) : 0.0;
     return P;
 }
 
@@ -179,7 +190,8 @@ bool config_ok(const sph_config* c)
     if (c->sinc_n != floor(c->sinc_n) || c->sinc_n < 3 || c->sinc_n > 9) return false;
     if (c->eos != SPH_EOS_IDEAL && c->eos != SPH_EOS_WEAKLY_COMPRESSIBLE) return false;
     if (c->precision != SPH_FP64 && c->precision != SPH_MIXED) return false;
-    if (c->reserved != 0) return false;
+    if (c->kernel_table != 0 && (c->kernel_table < 2 || c->kernel_table > SPH_KERNEL_TABLE_MAX))
+        return false;
     if (!(c->n_target > 0.0) || !(c->courant > 0.0) || !(c->dt_growth > 0.0)) return false;
     if (!(c->alpha_av >= 0.0)) return false;
     if (!(c->acc_dt >= 0.0) || !(c->energy_dt >= 0.0)) return false;
@@ -218,6 +230,10 @@ sph_status prepare(const sph_config* cfg, void* ws, sph_stream stream, Ctx& c)
     c.W = carve(ws, c.L);
     const bool fused = cfg->h_ratio_max <= kFusedKappaMax;
     c.P = make_params(cfg, sinc_bn((int)cfg->sinc_n), c.L.lcap, fused ? c.L.cand_cap : 0);
+    c.P.tabS = c.W.tabS;
+    c.P.tabD = c.W.tabD;
+    c.P.tabSf = c.W.tabSf;
+    c.P.tabDf = c.W.tabDf;
     c.s = (hipStream_t)stream;
     return SPH_OK;
 }
@@ -505,7 +521,7 @@ sph_status sph_step_backward(const sph_config* cfg, sph_particles* p, sph_global
     Ctx c;
     sph_status st = prepare(cfg, ws, stream, c);
     if (st) return st;
-    if (cfg->precision != SPH_FP64) return SPH_E_ARG;
+    if (cfg->precision != SPH_FP64 || cfg->kernel_table != 0) return SPH_E_ARG;
     if (!adj_ws || ((uintptr_t)adj_ws & 255)) return SPH_E_WORKSPACE;
     if (!step_args_ok(cfg, p, g) || !grads_ok(gout) || !grads_ok(gin)) return SPH_E_ARG;
     if ((st = step_rates(c, p, g))) return st;
@@ -520,6 +536,7 @@ sph_status sph_density_backward(const sph_config* cfg, const sph_particles* p, v
     sph_status st = prepare(cfg, ws, stream, c);
     if (st) return st;
     if (!adj_ws || ((uintptr_t)adj_ws & 255)) return SPH_E_WORKSPACE;
+    if (cfg->kernel_table != 0) return SPH_E_ARG;
     if (!p || !p->m || !rho_bar || !x_bar || !y_bar || !z_bar) return SPH_E_ARG;
     return hip_status(launch_density_backward(c.P, c.W, p, rho_bar, x_bar, y_bar, z_bar, adj_ws,
                                               c.s));

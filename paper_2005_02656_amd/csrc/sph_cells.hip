@@ -419,6 +419,29 @@ __global__ __launch_bounds__(kBlock) void k_pack_p4(const double* __restrict__ x
 
 }  // namespace
 
+// The kernel tables (section 4.5): entry i holds the values at nodes i and
+// i+1 of v_i = 2i/(N-1), from the same fitted polynomials as the direct
+// evaluation; dS_n/dv = (v dS_n/dv) / v, 0 at v = 0 (S_n is even in v).
+__global__ __launch_bounds__(kBlock) void k_fill_tables(Params P, double2* __restrict__ tS,
+                                                        double2* __restrict__ tD,
+                                                        float2* __restrict__ tSf,
+                                                        float2* __restrict__ tDf)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= P.tab_n - 1) return;
+    double S[2], D[2];
+    for (int k = 0; k < 2; ++k) {
+        const double v = (double)(i + k) / P.tab_inv_dv;
+        double vdS;
+        sinc_terms(kPiHalfSq * v * v, P.sinc_n, S[k], vdS);
+        D[k] = v > 0.0 ? vdS / v : 0.0;
+    }
+    tS[i] = make_double2(S[0], S[1]);
+    tD[i] = make_double2(D[0], D[1]);
+    tSf[i] = make_float2((float)S[0], (float)S[1]);
+    tDf[i] = make_float2((float)D[0], (float)D[1]);
+}
+
 hipError_t launch_clear_domain(const Ws& W, hipStream_t s)
 {
     k_clear_domain<<<1, 64, 0, s>>>(W.dom);
@@ -430,6 +453,9 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
 {
     const int64_t n = P.n;
     const int64_t nb = (n + kBlock - 1) / kBlock;
+    if (P.tab_n > 0)
+        k_fill_tables<<<(P.tab_n + kBlock - 1) / kBlock, kBlock, 0, s>>>(P, W.tabS, W.tabD,
+                                                                          W.tabSf, W.tabDf);
     k_domain_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t rg = nb < kRedGrid ? nb : kRedGrid;
     k_bbox<<<rg, kBlock, 0, s>>>(p->x, p->y, p->z, p->h, p->m, n, W.dom);

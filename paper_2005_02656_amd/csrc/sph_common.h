@@ -47,6 +47,14 @@ struct Params {
     int cand_cap;          // candidate-list capacity of the fused step (0: off)
     double wrapLd[3], wrapInvLd[3];  // L and 1/L on periodic axes, 0 on open ones
     float wrapL[3], wrapInvL[3];     // the same in FP32 (the fused step's candidate walk)
+    // kernel tables (section 4.5): tab_n values of S_n and dS_n/dv at v_i = i dv,
+    // dv = 2/(tab_n - 1), entry i holding the values at nodes i and i+1; 0 = off
+    int tab_n;
+    double tab_inv_dv;
+    const double2* tabS;
+    const double2* tabD;
+    const float2* tabSf;
+    const float2* tabDf;
 };
 
 // ---------------------------------------------------------------- device domain
@@ -182,6 +190,7 @@ int candidate_capacity(int ng_max);
 struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
     size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm, mf, mf2;
+    size_t tabS, tabD, tabSf, tabDf;
     size_t total;
     int64_t n, nsort_blocks, hist_len, scan_blocks, ncells_cap;
     int lcap, cand_cap;
@@ -208,6 +217,8 @@ struct Ws {
     void* recm;                // mixed precision: FP32 momentum records (aliases rec)
     float *mf, *mf2;           // mixed precision: FP32 mass and volume
     double* tmp;               // permute scratch (aliases the list area)
+    double2 *tabS, *tabD;      // kernel tables (kernel_table > 0), FP64 and FP32
+    float2 *tabSf, *tabDf;
 };
 Ws carve(void* ws, const Layout& L);
 
@@ -443,6 +454,70 @@ SPH_DEV double sinc_S(double t, int n)
 {
     const double s = horner(kSincS64, t);
     return pow_nm1(s, n) * s;
+}
+
+// Kernel lookup table (section 4.5): S_n at v = r/h by linear interpolation
+// between the two nodes around v, (1 - f) S_i + f S_{i+1}; likewise dS_n/dv.
+// The index is clamped to the last interval (v reaches 2 only to rounding).
+template <class T>
+SPH_DEV void tab_index(T v, T inv_dv, int n, int& i, T& f)
+{
+    const T s = v * inv_dv;
+    i = (int)s;
+    if (i > n - 2) i = n - 2;
+    f = s - (T)i;
+}
+
+// S_n and v dS_n/dv at t = (pi/2)^2 v^2: the fitted polynomials, or (kTab)
+// the tables; the hot kernels are compiled once per choice
+template <bool kTab>
+SPH_DEV void kern_terms_t(const Params& P, double t, double& S, double& vdS)
+{
+    if (kTab) {
+        const double v = sqrt(t) * (2.0 / kPi);
+        int i;
+        double f;
+        tab_index(v, P.tab_inv_dv, P.tab_n, i, f);
+        const double2 e = P.tabS[i], d = P.tabD[i];
+        S = (1.0 - f) * e.x + f * e.y;
+        vdS = v * ((1.0 - f) * d.x + f * d.y);
+    } else {
+        sinc_terms(t, P.sinc_n, S, vdS);
+    }
+}
+
+template <bool kTab>
+SPH_DEV double kern_S_t(const Params& P, double t)
+{
+    if (kTab) {
+        const double v = sqrt(t) * (2.0 / kPi);
+        int i;
+        double f;
+        tab_index(v, P.tab_inv_dv, P.tab_n, i, f);
+        const double2 e = P.tabS[i];
+        return (1.0 - f) * e.x + f * e.y;
+    }
+    return sinc_S(t, P.sinc_n);
+}
+
+// the same chosen at run time (the stage kernels)
+SPH_DEV void kern_terms(const Params& P, double t, double& S, double& vdS)
+{
+    if (P.tab_n > 0) kern_terms_t<true>(P, t, S, vdS);
+    else kern_terms_t<false>(P, t, S, vdS);
+}
+
+SPH_DEV double kern_S(const Params& P, double t)
+{
+    return P.tab_n > 0 ? kern_S_t<true>(P, t) : kern_S_t<false>(P, t);
+}
+
+// calls f(std::integral_constant<bool, kTab>) for the kernel evaluation of P
+template <class F>
+inline void with_table(const Params& P, F&& f)
+{
+    if (P.tab_n > 0) f(std::integral_constant<bool, true>{});
+    else f(std::integral_constant<bool, false>{});
 }
 
 // Largest number of wavefronts per SIMD for the neighbour-loop kernels (0: as

@@ -100,6 +100,43 @@ __device__ __forceinline__ float sinc_S_f(float t, int n)
     return pow_nm1(s, n) * s;
 }
 
+// the FP32 fits, or (kTab) the FP32 copies of the kernel tables (section 4.5)
+template <bool kTab>
+__device__ __forceinline__ void kern_terms_f_t(const Params& P, float t, float& S, float& vdS)
+{
+    if (kTab) {
+        const float v = sqrtf(t) * (float)(2.0 / kPi);
+        int i;
+        float f;
+        tab_index(v, (float)P.tab_inv_dv, P.tab_n, i, f);
+        const float2 e = P.tabSf[i], d = P.tabDf[i];
+        S = (1.0f - f) * e.x + f * e.y;
+        vdS = v * ((1.0f - f) * d.x + f * d.y);
+    } else {
+        sinc_terms_f(t, P.sinc_n, S, vdS);
+    }
+}
+
+template <bool kTab>
+__device__ __forceinline__ float kern_S_f_t(const Params& P, float t)
+{
+    if (kTab) {
+        const float v = sqrtf(t) * (float)(2.0 / kPi);
+        int i;
+        float f;
+        tab_index(v, (float)P.tab_inv_dv, P.tab_n, i, f);
+        const float2 e = P.tabSf[i];
+        return (1.0f - f) * e.x + f * e.y;
+    }
+    return sinc_S_f(t, P.sinc_n);
+}
+
+__device__ __forceinline__ void kern_terms_f(const Params& P, float t, float& S, float& vdS)
+{
+    if (P.tab_n > 0) kern_terms_f_t<true>(P, t, S, vdS);
+    else kern_terms_f_t<false>(P, t, S, vdS);
+}
+
 // positions as cell index + FP32 offset, and FP32 masses
 __global__ __launch_bounds__(kBlock) void k_pack_posm(Params P, const Domain* __restrict__ dom,
                                                       const double* __restrict__ x,
@@ -172,7 +209,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_densi
             float dx, dy, dz;
             const float r2 = disp_m(g, pa, q[u], dx, dy, dz);
             float S, vdS;
-            sinc_terms_f(r2 * tsc, P.sinc_n, S, vdS);
+            kern_terms_f(P, r2 * tsc, S, vdS);
             sS += (double)(mb[u] * S);
             sD += (double)(mb[u] * (3.0f * S + vdS));
         }
@@ -247,6 +284,7 @@ __device__ __forceinline__ void put_recm(const Domain* dom, void* rec, const Rec
     else ((RecMU*)rec)[a] = make_recmu(f);
 }
 
+template <bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m(Params P, Domain* __restrict__ dom,
                                                   const int32_t* __restrict__ nc,
                                                   const int32_t* __restrict__ list,
@@ -296,7 +334,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
             if (!ok[u]) continue;
             float dx, dy, dz;
             const float r2 = disp_m(g, pa, q[u], dx, dy, dz);
-            const float sw = vb[u] * (w0 * sinc_S_f(r2 * tsc, P.sinc_n));
+            const float sw = vb[u] * (w0 * kern_S_f_t<kTab>(P, r2 * tsc));
             const float sx = sw * dx, sy = sw * dy, sz = sw * dz;
             t11 += (double)(sx * dx);
             t12 += (double)(sx * dy);
@@ -376,7 +414,7 @@ SPH_DEV float nbr_c(const RecM& r, float) { return r.c; }
 SPH_DEV float nbr_m(const RecMU&, float m0) { return m0; }
 SPH_DEV float nbr_c(const RecMU&, float c0) { return c0; }
 
-template <class Rec>
+template <class Rec, bool kTab>
 __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __restrict__ dom,
                                                   const int32_t* __restrict__ nc,
                                                   const int32_t* __restrict__ ns,
@@ -439,12 +477,12 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
             float dx, dy, dz;
             const float r2 = disp_m(g, pa, qv[u], dx, dy, dz);
             float Wa = 0.0f;
-            if (gather) Wa = w0a * sinc_S_f(r2 * tsa, P.sinc_n);
+            if (gather) Wa = w0a * kern_S_f_t<kTab>(P, r2 * tsa);
             // support of W(h_b): v_b < 2, i.e. t_b < pi^2
             const float ih2 = rb.ih * rb.ih;
             const float tb = r2 * ((float)kPiHalfSq * ih2);
             float Wb = 0.0f;
-            if (tb < (float)(4.0 * kPiHalfSq)) Wb = bn * (ih2 * rb.ih) * sinc_S_f(tb, P.sinc_n);
+            if (tb < (float)(4.0 * kPiHalfSq)) Wb = bn * (ih2 * rb.ih) * kern_S_f_t<kTab>(P, tb);
             const float Aax = (ca11 * dx + ca12 * dy + ca13 * dz) * Wa;
             const float Aay = (ca12 * dx + ca22 * dy + ca23 * dz) * Wa;
             const float Aaz = (ca13 * dx + ca23 * dy + ca33 * dz) * Wa;
@@ -497,6 +535,7 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
 }
 
 // the record layout the uniformity flag selected when the records were written
+template <bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momentum_energy_m(Params P, Domain* __restrict__ dom,
                                                               const int32_t* __restrict__ nc,
                                                               const int32_t* __restrict__ ns,
@@ -510,9 +549,9 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
     if (dom->nonuniform)
-        momentum_energy_m<RecM>(P, dom, nc, ns, list, N, T, u, O, a);
+        momentum_energy_m<RecM, kTab>(P, dom, nc, ns, list, N, T, u, O, a);
     else
-        momentum_energy_m<RecMU>(P, dom, nc, ns, list, N, T, u, O, a);
+        momentum_energy_m<RecMU, kTab>(P, dom, nc, ns, list, N, T, u, O, a);
 }
 
 RecSrcM recm_src(const sph_particles* p)
@@ -560,9 +599,11 @@ hipError_t launch_iad_mixed(const Params& P, const Layout& L, const Ws& W, sph_p
     if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
     if (write_rec) launch_uniform_check(P, W, p, s);
     k_volume_m<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.mf2);
-    k_iad_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, pm, W.mf2, p->h, p->c11,
-                                            p->c12, p->c13, p->c22, p->c23, p->c33, recm_src(p),
-                                            write_rec ? W.recm : nullptr);
+    with_table(P, [&](auto tab) {
+        k_iad_m<decltype(tab)::value><<<grid_xcd(nb), kBlock, 0, s>>>(
+            P, W.dom, W.nc, W.list, pm, W.mf2, p->h, p->c11, p->c12, p->c13, p->c22, p->c23,
+            p->c33, recm_src(p), write_rec ? W.recm : nullptr);
+    });
     return hipGetLastError();
 }
 
@@ -582,8 +623,10 @@ hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const 
                p->m};
     NbrM N{(const RecM*)W.recm, (const RecMU*)W.recm, pm};
     k_dtmin_begin_m<<<1, 1, 0, s>>>(W.dom);
-    k_momentum_energy_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list, N, T,
-                                                        p->u, O);
+    with_table(P, [&](auto tab) {
+        k_momentum_energy_m<decltype(tab)::value><<<grid_xcd(nb), kBlock, 0, s>>>(
+            P, W.dom, W.nc, W.ns, W.list, N, T, p->u, O);
+    });
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_PAIR) void k_densit
             double dx, dy, dz;
             double r2 = disp(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
             double S, vdS;
-            sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
+            kern_terms(P, r2 * tsc, S, vdS);
             sS += mb[u] * S;
             sD += mb[u] * (3.0 * S + vdS);
         }
@@ -147,6 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_uniform_check(int64_t n, const doubl
     if (__ballot(diff) && (threadIdx.x & 63) == 0) atomicOr(&dom->nonuniform, 1u);
 }
 
+template <bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Params P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ list,
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
             if (!ok[u]) continue;
             double dx, dy, dz;
             double r2 = disp(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
-            double s = q[u].v * (w0 * sinc_S(r2 * tsc, P.sinc_n));
+            double s = q[u].v * (w0 * kern_S_t<kTab>(P, r2 * tsc));
             t11 += s * dx * dx;
             t12 += s * dx * dy;
             t13 += s * dx * dz;
@@ -282,7 +283,7 @@ SPH_DEV double nbr_m(const MomNbr& r, double) { return r.m; }
 SPH_DEV double nbr_c(const MomNbr& r, double) { return r.c; }
 SPH_DEV double nbr_m(const MomNbrU&, double m0) { return m0; }
 SPH_DEV double nbr_c(const MomNbrU&, double c0) { return c0; }
-template <class Rec, int kMomBatch>
+template <class Rec, int kMomBatch, bool kTab>
 __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ ns,
@@ -328,12 +329,12 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
             double dx, dy, dz;
             double r2 = disp(P, xa, ya, za, rb.x, rb.y, rb.z, dx, dy, dz);
             double Wa = 0.0;
-            if (gather) Wa = w0a * sinc_S(r2 * tsa, P.sinc_n);
+            if (gather) Wa = w0a * kern_S_t<kTab>(P, r2 * tsa);
             // W(r, h_b) on its support t_b < pi^2 (v_b < 2)
             double Wb = 0.0;
             const double ih = rb.ih, ih2 = ih * ih;
             const double tb = r2 * (kPiHalfSq * ih2);
-            if (tb < 4.0 * kPiHalfSq) Wb = P.bn * (ih2 * ih) * sinc_S(tb, P.sinc_n);
+            if (tb < 4.0 * kPiHalfSq) Wb = P.bn * (ih2 * ih) * kern_S_t<kTab>(P, tb);
             // A_ab(h_a) = C_a d W_a and K_b d with d = x_b - x_a
             const double Aax = (ca11 * dx + ca12 * dy + ca13 * dz) * Wa;
             const double Aay = (ca12 * dx + ca22 * dy + ca23 * dz) * Wa;
@@ -411,6 +412,7 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
 // third wavefront per SIMD with batches of 3 (52.7 ms against 54.9 at two
 // wavefronts and batches of 4, 64 M particles); the 144-byte records spill
 // at three.
+template <bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
@@ -425,9 +427,10 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
-    momentum_energy<MomNbr, SPH_MOM_BATCH>(P, dom, nc, ns, list, rec, T, u, O, a);
+    momentum_energy<MomNbr, SPH_MOM_BATCH, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
 }
 
+template <bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_MOM_U_ATTR void k_momentum_energy_u(Params P, Domain* __restrict__ dom,
                                                                 const int32_t* __restrict__ nc,
                                                                 const int32_t* __restrict__ ns,
@@ -442,7 +445,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_U_ATTR void k_momentum_energy_u(Par
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
-    momentum_energy<MomNbrU, SPH_MOM_U_BATCH>(P, dom, nc, ns, list, rec, T, u, O, a);
+    momentum_energy<MomNbrU, SPH_MOM_U_BATCH, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
 }
 
 __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals* g)
@@ -487,9 +490,11 @@ hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particl
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.p4, W.vol, W.pv);
     if (write_rec) launch_uniform_check(P, W, p, s);
-    k_iad<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12,
-                                          p->c13, p->c22, p->c23, p->c33, rec_src(p),
-                                          write_rec ? (void*)W.rec : nullptr);
+    with_table(P, [&](auto tab) {
+        k_iad<decltype(tab)::value><<<grid_xcd(nb), kBlock, 0, s>>>(
+            P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12, p->c13, p->c22, p->c23, p->c33,
+            rec_src(p), write_rec ? (void*)W.rec : nullptr);
+    });
     return hipGetLastError();
 }
 
@@ -525,10 +530,13 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
     MomSelf T{p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p,
               p->h, p->m, p->c};
     k_dtmin_begin<<<1, 1, 0, s>>>(W.dom);
-    k_momentum_energy_u<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list,
-                                                        (const MomNbrU*)W.rec, T, p->u, O);
-    k_momentum_energy<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.ns, W.list,
-                                                      (const MomNbr*)W.rec, T, p->u, O);
+    with_table(P, [&](auto tab) {
+        constexpr bool kTab = decltype(tab)::value;
+        k_momentum_energy_u<kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+            P, W.dom, W.nc, W.ns, W.list, (const MomNbrU*)W.rec, T, p->u, O);
+        k_momentum_energy<kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+            P, W.dom, W.nc, W.ns, W.list, (const MomNbr*)W.rec, T, p->u, O);
+    });
     return hipGetLastError();
 }
 

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_update_h(Params P, const Domain* __r
                        double r2 = disp(P, xa, ya, za, q.x, q.y, q.z, dx, dy, dz);
                        if (r2 < R2) {
                            double S, vdS;
-                           sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
+                           kern_terms(P, r2 * tsc, S, vdS);
                            sS += S;
                            sV += vdS;
                        }
@@ -489,7 +489,7 @@ __device__ __forceinline__ void pair_gather_xyz(const Pos4* __restrict__ p4, int
     z = odd ? B.x : r0;
 }
 
-template <int kPer>
+template <int kPer, bool kTab>
 __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restrict__ dom,
                                               const int32_t* __restrict__ nk,
                                               const int32_t* __restrict__ cand,
@@ -533,7 +533,7 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
                 double r2 = disp_p<kPer>(P, xa, ya, za, qx[u], qy[u], qz[u], dx, dy, dz);
                 if (j0 + u < cnt && r2 < R2) {
                     double S, vdS;
-                    sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
+                    kern_terms_t<kTab>(P, r2 * tsc, S, vdS);
                     sS += S;
                     sV += vdS;
                 }
@@ -552,28 +552,28 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
     }
 }
 
-template <int kPer>
+template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
     double lam)
 {
-    update_h_list<kPer>(P, dom, nk, cand, p4, h, lam);
+    update_h_list<kPer, kTab>(P, dom, nk, cand, p4, h, lam);
 }
-template <int kPer>
+template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list_full(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
     double lam)
 {
     if (dom->refit == 0u) return;
-    update_h_list<kPer>(P, dom, nk, cand, p4, h, lam);
+    update_h_list<kPer, kTab>(P, dom, nk, cand, p4, h, lam);
 }
 
 // exact lists from the candidates with the final h (same layout as k_find_neighbors)
 // kDens: also the density sums over the gather members (the same order as the
 // density pass over the gather list), then rho, Omega and the EOS
-template <bool kDens, int kPer>
+template <bool kDens, int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Domain* __restrict__ dom,
                                                    const int32_t* __restrict__ nk,
                                                    const int32_t* __restrict__ cand,
@@ -641,7 +641,7 @@ __global__ __launch_bounds__(kBlock) SPH_FILTER_ATTR void k_filter(Params P, Dom
                     list[lpos(a, cg, ng)] = b;
                     if (kDens) {
                         double S, vdS;
-                        sinc_terms(r2 * tsc, P.sinc_n, S, vdS);
+                        kern_terms_t<kTab>(P, r2 * tsc, S, vdS);
                         sS += mb[u] * S;
                         sD += mb[u] * (3.0 * S + vdS);
                     }
@@ -720,16 +720,22 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     mk.at(1, s);
     if (P.newton_iters > 0) {
         with_periodic(P, [&](auto per) {
-            constexpr int kPer = decltype(per)::value;
-            k_update_h_list<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
-                                                                  p->h, lam);
+            with_table(P, [&](auto tab) {
+                constexpr int kPer = decltype(per)::value;
+                constexpr bool kTab = decltype(tab)::value;
+                k_update_h_list<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+                    P, W.dom, W.nk, W.cand, W.p4, p->h, lam);
+            });
         });
         if (lam < P.kappa) {
             launch_candidates(true, P, W, P.kappa, s);
             with_periodic(P, [&](auto per) {
-                constexpr int kPer = decltype(per)::value;
-                k_update_h_list_full<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(
-                    P, W.dom, W.nk, W.cand, W.p4, p->h, P.kappa);
+                with_table(P, [&](auto tab) {
+                    constexpr int kPer = decltype(per)::value;
+                    constexpr bool kTab = decltype(tab)::value;
+                    k_update_h_list_full<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+                        P, W.dom, W.nk, W.cand, W.p4, p->h, P.kappa);
+                });
             });
         }
     }
@@ -738,13 +744,16 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     if (e != hipSuccess) return e;
     const DensOut O{p->m, p->u, p->p_ref, p->rho_ref, p->rho, p->omega, p->p, p->c};
     with_periodic(P, [&](auto per) {
-        constexpr int kPer = decltype(per)::value;
-        if (with_density)
-            k_filter<true, kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
-                                                                 W.nc, W.ns, W.list, O);
-        else
-            k_filter<false, kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nk, W.cand, W.p4,
-                                                                  W.nc, W.ns, W.list, O);
+        with_table(P, [&](auto tab) {
+            constexpr int kPer = decltype(per)::value;
+            constexpr bool kTab = decltype(tab)::value;
+            if (with_density)
+                k_filter<true, kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+                    P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns, W.list, O);
+            else
+                k_filter<false, kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+                    P, W.dom, W.nk, W.cand, W.p4, W.nc, W.ns, W.list, O);
+        });
     });
     return hipGetLastError();
 }

@@ -24,6 +24,8 @@ STATUS_NAMES = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_WORKSPACE
 ERRBIT_NEIGHBOR_OVERFLOW, ERRBIT_CELL_RANGE, ERRBIT_NONFINITE, ERRBIT_SINGULAR_TAU = 1, 2, 4, 8
 SHORT_REACH = 1.03   # SPH_SHORT_REACH: the fused step's short candidate reach lambda
 STATIC_SCRATCH_BYTES = 64 << 20   # SPH_STATIC_SCRATCH_BYTES: sph_step_static's scratch
+KERNEL_TABLE_MAX = 65536          # SPH_KERNEL_TABLE_MAX
+KERNEL_TABLE_PAPER = 20000        # the table size of section 4.5
 FP64, MIXED = 0, 1
 
 STATE_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",
@@ -47,7 +49,7 @@ class _Config(C.Structure):
                 ("h_ratio_max", C.c_double), ("gamma", C.c_double), ("c0", C.c_double),
                 ("alpha_av", C.c_double), ("courant", C.c_double), ("dt_growth", C.c_double),
                 ("acc_dt", C.c_double), ("energy_dt", C.c_double),
-                ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("precision", C.c_int32), ("kernel_table", C.c_int32)]
 
 
 GRAD_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "u", "du_m1")
@@ -83,6 +85,7 @@ class Config:
     acc_dt: float = 0.2
     energy_dt: float = 0.2
     precision: int = FP64
+    kernel_table: int = 0   # 0: direct kernel; N: the N-entry table of section 4.5
 
     @classmethod
     def from_params(cls, n: int, params: dict, **kw) -> "Config":
@@ -114,7 +117,7 @@ class Config:
         s.acc_dt = float(self.acc_dt)
         s.energy_dt = float(self.energy_dt)
         s.precision = int(self.precision)
-        s.reserved = 0
+        s.kernel_table = int(self.kernel_table)
         return s
 
 

@@ -36,6 +36,7 @@ def test_constants_match_the_header(sph):
     src = open(os.path.join(ROOT, "include", "sph.h")).read()
     defs = dict(re.findall(r"#define (SPH_\w+) (.+)", src))
     assert float(defs["SPH_SHORT_REACH"]) == sph.SHORT_REACH
+    assert int(defs["SPH_KERNEL_TABLE_MAX"]) == sph.KERNEL_TABLE_MAX
     m = re.fullmatch(r"\((\d+)u << (\d+)\)", defs["SPH_STATIC_SCRATCH_BYTES"].strip())
     assert int(m.group(1)) << int(m.group(2)) == sph.STATIC_SCRATCH_BYTES
     assert int(defs["SPH_STEP_PHASES"]) == len(sph.STEP_PHASES)
@@ -54,9 +55,13 @@ def test_workspace_bytes_validation(sph):
     for bad in (good.replace(n=0), good.replace(ng_max=0), good.replace(sinc_n=2.5),
                 good.replace(sinc_n=12.0), good.replace(eos=7), good.replace(h_ratio_max=1.0),
                 good.replace(precision=3), good.replace(eos=1, c0=0.0),
-                good.replace(box_hi=(1.0, 0.0, 1.0))):
+                good.replace(box_hi=(1.0, 0.0, 1.0)), good.replace(kernel_table=1),
+                good.replace(kernel_table=sph.KERNEL_TABLE_MAX + 1)):
         assert L.sph_workspace_bytes(C.byref(bad.c())) == 0
     assert L.sph_workspace_bytes(None) == 0
+    for ok in (2, sph.KERNEL_TABLE_PAPER, sph.KERNEL_TABLE_MAX):
+        assert L.sph_workspace_bytes(C.byref(good.replace(kernel_table=ok).c())) == \
+            L.sph_workspace_bytes(C.byref(good.c()))
 
 
 def test_argument_errors_are_synchronous(sph):
