@@ -312,6 +312,56 @@ def sort_keys(keys):
     return perm
 
 
+# --------------------------------------------------------------------------- gravity
+def gravity_leaf_level(n: int) -> int:
+    """Deepest level L of the gravity tree: the largest L <= 9 with 8^L <= n."""
+    L = 0
+    while L < 9 and 8 ** (L + 1) <= max(n, 1):
+        L += 1
+    return L
+
+
+def gravity_direct(x, y, z, m, G, eps, targets=None):
+    """(gx, gy, gz, scale): the softened Newtonian sum over all pairs."""
+    x, y, z, m = map(_f64, (x, y, z, m))
+    n = x.size
+    nt, t = _targets(n, targets)
+    out = [np.full(n, np.nan) for _ in range(4)]
+    lib().ora_gravity_direct(C.c_int64(n), _p(x), _p(y), _p(z), _p(m), C.c_double(G),
+                             C.c_double(eps), C.c_int64(nt), _p(t), *[_p(o) for o in out])
+    return tuple(out)
+
+
+def moments(idx, x, y, z, m):
+    """[M, cx, cy, cz, Q11, Q12, Q13, Q22, Q23, Q33] of the particles idx."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    x, y, z, m = map(_f64, (x, y, z, m))
+    out = np.zeros(10)
+    lib().ora_moments(C.c_int64(idx.size), _p(idx), _p(x), _p(y), _p(z), _p(m), _p(out))
+    return out
+
+
+def multipole_accel(mo, pos, G, eps):
+    mo, pos = _f64(mo), _f64(pos)
+    g = np.zeros(3)
+    lib().ora_multipole_accel(_p(mo), _p(pos), C.c_double(G), C.c_double(eps), _p(g))
+    return g
+
+
+def gravity_tree(x, y, z, m, lo, hi, L, G, eps, theta, targets=None):
+    """(gx, gy, gz, scale): the multipole tree walk of section 4.1 (see the C
+    header comment for the tree, the opening rule and the expansion)."""
+    x, y, z, m = map(_f64, (x, y, z, m))
+    lo, hi = _f64(lo), _f64(hi)
+    n = x.size
+    nt, t = _targets(n, targets)
+    out = [np.full(n, np.nan) for _ in range(4)]
+    lib().ora_gravity_tree(C.c_int64(n), _p(x), _p(y), _p(z), _p(m), _p(lo), _p(hi),
+                           C.c_int(int(L)), C.c_double(G), C.c_double(eps),
+                           C.c_double(theta), C.c_int64(nt), _p(t), *[_p(o) for o in out])
+    return tuple(out)
+
+
 # --------------------------------------------------------------------------- composed
 def initial_h(cfg, st, iters=12, kappa=8.0):
     """Untimed set-up: `iters` Newton steps from the generator's guess, clamped at

@@ -684,6 +684,219 @@ void ora_sort_keys(int64_t n, const uint64_t* keys, int64_t* perm)
     g_sort_keys = NULL;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Self-gravity (section 4.1: a multipole expansion evaluated on the same    */
+/* octree that finds the neighbours; order, opening rule and softening not   */
+/* printed, readings):                                                       */
+/*   g_a = -G sum_{b != a} m_b (x_a - x_b) / (|x_a - x_b|^2 + eps^2)^(3/2)    */
+/* (Plummer softening eps), approximated on the octree of the particle keys. */
+/* ------------------------------------------------------------------------ */
+
+/* The exact definition by direct summation over all b in ascending index. */
+void ora_gravity_direct(int64_t n, const double* x, const double* y, const double* z,
+                        const double* m, double G, double eps, int64_t nt,
+                        const int64_t* targets, double* gx, double* gy, double* gz,
+                        double* scale)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t a = ora_tgt(targets, t);
+        double acc[3] = {0, 0, 0}, sc = 0.0;
+        for (int64_t b = 0; b < n; ++b) {
+            if (b == a) continue;
+            double d[3] = {x[a] - x[b], y[a] - y[b], z[a] - z[b]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+            double f = G * m[b] / (r2 * sqrt(r2));
+            for (int k = 0; k < 3; ++k) acc[k] -= f * d[k];
+            sc += f * sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        }
+        gx[a] = acc[0];
+        gy[a] = acc[1];
+        gz[a] = acc[2];
+        if (scale) scale[a] = sc;
+    }
+}
+
+/* Monopole and quadrupole moments of a set of particles (indices idx[0..k)):
+ * M, the centre of mass c and the traceless quadrupole
+ *   Q_ij = sum m (3 d_i d_j - |d|^2 delta_ij),  d = x_b - c,
+ * packed as [M, cx, cy, cz, Q11, Q12, Q13, Q22, Q23, Q33]. */
+void ora_moments(int64_t k, const int64_t* idx, const double* x, const double* y,
+                 const double* z, const double* m, double* out)
+{
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t i = 0; i < k; ++i) {
+        int64_t b = idx[i];
+        M += m[b];
+        sx += m[b] * x[b];
+        sy += m[b] * y[b];
+        sz += m[b] * z[b];
+    }
+    double c[3] = {0, 0, 0};
+    if (M > 0.0) { c[0] = sx / M; c[1] = sy / M; c[2] = sz / M; }
+    double Q[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < k; ++i) {
+        int64_t b = idx[i];
+        double d[3] = {x[b] - c[0], y[b] - c[1], z[b] - c[2]};
+        double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        Q[0] += m[b] * (3.0 * d[0] * d[0] - d2);
+        Q[1] += m[b] * (3.0 * d[0] * d[1]);
+        Q[2] += m[b] * (3.0 * d[0] * d[2]);
+        Q[3] += m[b] * (3.0 * d[1] * d[1] - d2);
+        Q[4] += m[b] * (3.0 * d[1] * d[2]);
+        Q[5] += m[b] * (3.0 * d[2] * d[2] - d2);
+    }
+    out[0] = M; out[1] = c[0]; out[2] = c[1]; out[3] = c[2];
+    for (int j = 0; j < 6; ++j) out[4 + j] = Q[j];
+}
+
+/* Acceleration at x of the expansion (mo as ora_moments packs it) to second
+ * order, with the Plummer-softened distance rho^2 = |r|^2 + eps^2, r = x - c:
+ *   g = -G M r / rho^3 + G (Q r / rho^5 - (5/2) (r.Q.r) r / rho^7). */
+void ora_multipole_accel(const double* mo, const double* x, double G, double eps,
+                         double* g)
+{
+    double r[3] = {x[0] - mo[1], x[1] - mo[2], x[2] - mo[3]};
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps * eps;
+    double ir = 1.0 / sqrt(r2);
+    double ir2 = ir * ir;
+    double ir3 = ir * ir2, ir5 = ir3 * ir2, ir7 = ir5 * ir2;
+    const double* Q = mo + 4;
+    double Qr[3] = {Q[0] * r[0] + Q[1] * r[1] + Q[2] * r[2],
+                    Q[1] * r[0] + Q[3] * r[1] + Q[4] * r[2],
+                    Q[2] * r[0] + Q[4] * r[1] + Q[5] * r[2]};
+    double rQr = r[0] * Qr[0] + r[1] * Qr[1] + r[2] * Qr[2];
+    for (int k = 0; k < 3; ++k)
+        g[k] = -G * mo[0] * r[k] * ir3 + G * (Qr[k] * ir5 - 2.5 * rQr * r[k] * ir7);
+}
+
+/* The tree: the particles in the stable order of their keys (key domain lo/hi
+ * as ora_morton_keys); the node of level l (0..L) with prefix P holds the
+ * particles whose key shifted right by 3(21-l) equals P; its size is the
+ * largest extent of the key domain over 2^l.  Walk per target, depth first
+ * from the root, children in ascending prefix:
+ *   - a node holding the target's own key prefix is opened;
+ *   - otherwise a node whose size s and distance d = |x_a - c| satisfy
+ *     s < theta d (tested as s^2 < theta^2 d^2) contributes its expansion;
+ *   - an opened node of level L contributes its particles b != a directly
+ *     (in key order), an opened node above L its children.
+ * theta = 0 opens every node and so sums every pair directly. */
+typedef struct {
+    int64_t start, end;   /* range in the sorted order */
+    uint64_t prefix;
+    double mo[10];
+} ora_gnode;
+
+typedef struct {
+    int L;
+    int64_t count[10];
+    ora_gnode* lev[10];
+    const int64_t* order;     /* sorted position -> particle */
+    const uint64_t* skeys;    /* keys in sorted order */
+    double size[10];
+} ora_gtree;
+
+static void ora_gwalk(const ora_gtree* T, int l, int64_t node, int64_t a, uint64_t ka,
+                      const double* x, const double* y, const double* z, const double* m,
+                      double G, double eps, double theta, double acc[3], double* sc)
+{
+    const ora_gnode* nd = &T->lev[l][node];
+    const int sh = 3 * (21 - l);
+    const double xa[3] = {x[a], y[a], z[a]};
+    int open = (ka >> sh) == nd->prefix;
+    if (!open) {
+        double d[3] = {xa[0] - nd->mo[1], xa[1] - nd->mo[2], xa[2] - nd->mo[3]};
+        double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (T->size[l] * T->size[l] < theta * theta * d2) {
+            double g[3];
+            ora_multipole_accel(nd->mo, xa, G, eps, g);
+            for (int k = 0; k < 3; ++k) acc[k] += g[k];
+            *sc += sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+            return;
+        }
+    }
+    if (l == T->L) {
+        for (int64_t i = nd->start; i < nd->end; ++i) {
+            int64_t b = T->order[i];
+            if (b == a) continue;
+            double d[3] = {xa[0] - x[b], xa[1] - y[b], xa[2] - z[b]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+            double f = G * m[b] / (r2 * sqrt(r2));
+            for (int k = 0; k < 3; ++k) acc[k] -= f * d[k];
+            *sc += f * sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        }
+        return;
+    }
+    /* children: the nodes of level l+1 with prefixes 8P .. 8P+7 */
+    const ora_gnode* ch = T->lev[l + 1];
+    int64_t lo = 0, hi = T->count[l + 1];
+    while (lo < hi) {   /* first child with prefix >= 8P */
+        int64_t mid = (lo + hi) / 2;
+        if (ch[mid].prefix < nd->prefix * 8) lo = mid + 1; else hi = mid;
+    }
+    for (int64_t c = lo; c < T->count[l + 1] && ch[c].prefix < nd->prefix * 8 + 8; ++c)
+        ora_gwalk(T, l + 1, c, a, ka, x, y, z, m, G, eps, theta, acc, sc);
+}
+
+void ora_gravity_tree(int64_t n, const double* x, const double* y, const double* z,
+                      const double* m, const double* lo, const double* hi, int L, double G,
+                      double eps, double theta, int64_t nt, const int64_t* targets,
+                      double* gx, double* gy, double* gz, double* scale)
+{
+    if (L < 0 || L > 9) return;
+    uint64_t* keys = malloc(sizeof(uint64_t) * n);
+    int64_t* order = malloc(sizeof(int64_t) * n);
+    uint64_t* skeys = malloc(sizeof(uint64_t) * n);
+    ora_morton_keys(n, x, y, z, lo, hi, keys);
+    ora_sort_keys(n, keys, order);
+    for (int64_t i = 0; i < n; ++i) skeys[i] = keys[order[i]];
+    ora_gtree T;
+    T.L = L;
+    T.order = order;
+    T.skeys = skeys;
+    double ext = 0.0;
+    for (int k = 0; k < 3; ++k)
+        if (hi[k] - lo[k] > ext) ext = hi[k] - lo[k];
+    for (int l = 0; l <= L; ++l) {
+        T.size[l] = ext / (double)(1 << l);
+        const int sh = 3 * (21 - l);
+        /* the nodes of level l: runs of equal prefix in the sorted keys */
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (i == 0 || (skeys[i] >> sh) != (skeys[i - 1] >> sh)) ++cnt;
+        T.count[l] = cnt;
+        T.lev[l] = malloc(sizeof(ora_gnode) * (cnt > 0 ? cnt : 1));
+        int64_t j = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (i == 0 || (skeys[i] >> sh) != (skeys[i - 1] >> sh)) {
+                ++j;
+                T.lev[l][j].start = i;
+                T.lev[l][j].prefix = skeys[i] >> sh;
+            }
+            T.lev[l][j].end = i + 1;
+        }
+        for (int64_t c = 0; c < cnt; ++c) {
+            ora_gnode* nd = &T.lev[l][c];
+            ora_moments(nd->end - nd->start, order + nd->start, x, y, z, m, nd->mo);
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t a = ora_tgt(targets, t);
+        double acc[3] = {0, 0, 0}, sc = 0.0;
+        if (T.count[0] > 0)
+            ora_gwalk(&T, 0, 0, a, keys[a], x, y, z, m, G, eps, theta, acc, &sc);
+        gx[a] = acc[0];
+        gy[a] = acc[1];
+        gz[a] = acc[2];
+        if (scale) scale[a] = sc;
+    }
+    for (int l = 0; l <= L; ++l) free(T.lev[l]);
+    free(keys);
+    free(order);
+    free(skeys);
+}
+
 /* threads the OpenMP loops above run on */
 #ifdef _OPENMP
 #include <omp.h>
