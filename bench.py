@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
                     [--precision fp64|mixed] [--no-cpu-baseline] [--no-mixed]
-                    [--no-adjoint] [--no-table] [--oracle-points]
+                    [--no-adjoint] [--no-table] [--no-gravity] [--oracle-points]
 
 A step is one sph_step (Morton sort into cells, Newton h update, neighbour
 search, density, IAD, momentum/energy with AV, global dt, integration and
@@ -13,8 +13,8 @@ reference density) is untimed.  The timed steps run through sph_step_marked
 the roofline of the longest phase come from the timed steps themselves.  Then,
 unless switched off: the same workload in mixed precision, the kernel
 lookup-table variant (FP64 and mixed), the adjoint/forward
-time of the 64^3 rollout, and the FP64 oracle timed on the host on a bounded
-sample.  Prints ONE JSON line.
+time of the 64^3 rollout, the self-gravity tree walk on an 8 M-particle sphere,
+and the FP64 oracle timed on the host on a bounded sample.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision timing of the same workload")
+    ap.add_argument("--no-gravity", action="store_true",
+                    help="skip the timing of the self-gravity tree walk")
     ap.add_argument("--no-table", action="store_true",
                     help="skip the timing of the kernel lookup-table variant")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -193,6 +195,35 @@ def adjoint_timing(sph, inputs, torch, steps=20, ckpt=5):
                         f"every {ckpt}, loss 1/2|rho - rho*|^2, gradient w.r.t. v0",
             "forward_ms": fwd, "backward_ms": bwd, "adjoint_over_forward": bwd / fwd,
             "loss": float(loss.item()), "grad_norm": float(v0.grad.norm().item())}
+
+
+def gravity_timing(sph, inputs, torch, n=8_000_000, theta=0.5, eps=1e-3, reps=3):
+    """sph_gravity on an Evrard sphere (rho = 1/(2 pi r), radius and mass 1) at
+    opening angle theta: tree build and walk, after the cell build."""
+    w = inputs.evrard_sphere(n)
+    cfg = sph.Config.from_params(w.n, w.params)
+    parts = sph.Particles.from_arrays(w.arrays, cfg)
+    ws = sph.Workspace(cfg)
+    sph.workspace_init(cfg, ws)
+    gws = sph.GravityWorkspace(cfg)
+    sph.build_cells(cfg, parts, ws)
+    out = sph.gravity(cfg, parts, ws, gws, 1.0, eps, theta)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sph.gravity(cfg, parts, ws, gws, 1.0, eps, theta, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    st, bits = sph.status_sync(ws)
+    if st:
+        raise RuntimeError(f"gravity raised {sph.status_string(st)} (bits {bits})")
+    res = {"workload": f"Evrard sphere, {n} particles, theta {theta}, Plummer eps {eps}",
+           "ms": ms, "particles_per_s": n / (ms * 1e-3)}
+    del parts, ws, gws, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(side):
@@ -392,6 +423,10 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(sph, inputs, torch)
         log(f"[bench] adjoint rollout: {out['adjoint']}")
+
+    if not args.no_gravity:
+        out["gravity"] = gravity_timing(sph, inputs, torch)
+        log(f"[bench] gravity: {out['gravity']}")
 
     if args.calib_copy_mib > 0:
         # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE counters calibrate

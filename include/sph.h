@@ -216,6 +216,39 @@ sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, voi
 sph_status sph_step_marked(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
                            sph_stream stream, void* const* events, int32_t nevents);
 
+/* ------------------------------------------------------------------------
+ * Self-gravity (section 4.1: a multipole expansion evaluated on the same
+ * octree that finds the neighbours).  Plummer-softened Newtonian gravity
+ *   g_a = -G sum_{b != a} m_b (x_a - x_b) / (|x_a - x_b|^2 + eps^2)^(3/2),
+ * evaluated on the octree of the Morton keys of the last sph_build_cells: the
+ * node of level l (0 .. L, L the deepest level with 8^L <= n, at most 9) holds
+ * the particles whose key prefix of 3l bits is its index.  Each node carries
+ * its mass, centre of mass c and traceless quadrupole
+ * Q = sum m (3 d d^T - |d|^2 I), d = x - c.  A target walks the tree depth first
+ * from the root, children in ascending prefix: the node holding the target is
+ * opened; another node of size s (the key domain's largest extent over 2^l) at
+ * distance d = |x_a - c| contributes, when s < theta d, its expansion
+ *   -G M r / rho^3 + G (Q r / rho^5 - (5/2)(r.Q.r) r / rho^7),
+ *   r = x_a - c, rho^2 = |r|^2 + eps^2;
+ * an opened leaf contributes its particles b != a directly.  theta = 0 gives
+ * the direct sum.  Open boundaries only (no periodic images).
+ * In: x y z m in the slot order of the last sph_build_cells on ws (call it
+ * first).  Out: gx gy gz per slot (device, caller-owned, length n).
+ * gws: caller-owned gravity workspace of sph_gravity_workspace_bytes(cfg)
+ * bytes, 256-byte aligned, used only by this call.
+ * Errors: SPH_E_ARG for a periodic axis, NULL arrays, negative or non-finite
+ * G, eps or theta; SPH_E_WORKSPACE for a NULL or misaligned ws or gws. */
+typedef struct {
+    double G;       /* gravitational constant */
+    double eps;     /* Plummer softening length, >= 0 */
+    double theta;   /* opening angle: a node is expanded when size < theta * distance */
+} sph_gravity_params;
+
+size_t sph_gravity_workspace_bytes(const sph_config* cfg);
+sph_status sph_gravity(const sph_config* cfg, const sph_particles* p,
+                       const sph_gravity_params* gp, void* ws, void* gws, double* gx,
+                       double* gy, double* gz, sph_stream stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): sph_step
  * without a caller workspace.  Its scratch is a fixed device array of

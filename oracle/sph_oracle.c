@@ -720,11 +720,14 @@ void ora_gravity_direct(int64_t n, const double* x, const double* y, const doubl
 /* Monopole and quadrupole moments of a set of particles (indices idx[0..k)):
  * M, the centre of mass c and the traceless quadrupole
  *   Q_ij = sum m (3 d_i d_j - |d|^2 delta_ij),  d = x_b - c,
- * packed as [M, cx, cy, cz, Q11, Q12, Q13, Q22, Q23, Q33]. */
+ * packed as [M, cx, cy, cz, Q11, Q12, Q13, Q22, Q23, Q33].  The sums over a
+ * node run in extended precision (long double): a node can hold millions of
+ * particles, and a running double sum of that length would lose more than the
+ * 1e-12 the accelerations are compared at; the terms themselves are doubles. */
 void ora_moments(int64_t k, const int64_t* idx, const double* x, const double* y,
                  const double* z, const double* m, double* out)
 {
-    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    long double M = 0.0L, sx = 0.0L, sy = 0.0L, sz = 0.0L;
     for (int64_t i = 0; i < k; ++i) {
         int64_t b = idx[i];
         M += m[b];
@@ -733,8 +736,8 @@ void ora_moments(int64_t k, const int64_t* idx, const double* x, const double* y
         sz += m[b] * z[b];
     }
     double c[3] = {0, 0, 0};
-    if (M > 0.0) { c[0] = sx / M; c[1] = sy / M; c[2] = sz / M; }
-    double Q[6] = {0, 0, 0, 0, 0, 0};
+    if (M > 0.0L) { c[0] = (double)(sx / M); c[1] = (double)(sy / M); c[2] = (double)(sz / M); }
+    long double Q[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = 0; i < k; ++i) {
         int64_t b = idx[i];
         double d[3] = {x[b] - c[0], y[b] - c[1], z[b] - c[2]};
@@ -746,8 +749,8 @@ void ora_moments(int64_t k, const int64_t* idx, const double* x, const double* y
         Q[4] += m[b] * (3.0 * d[1] * d[2]);
         Q[5] += m[b] * (3.0 * d[2] * d[2] - d2);
     }
-    out[0] = M; out[1] = c[0]; out[2] = c[1]; out[3] = c[2];
-    for (int j = 0; j < 6; ++j) out[4 + j] = Q[j];
+    out[0] = (double)M; out[1] = c[0]; out[2] = c[1]; out[3] = c[2];
+    for (int j = 0; j < 6; ++j) out[4 + j] = (double)Q[j];
 }
 
 /* Acceleration at x of the expansion (mo as ora_moments packs it) to second

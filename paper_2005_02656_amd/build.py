@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsph.so")
 SOURCES = ["sph_api.hip", "sph_cells.hip", "sph_search.hip", "sph_pairs.hip",
-           "sph_mixed.hip", "sph_integrate.hip", "sph_adjoint.hip"]
+           "sph_mixed.hip", "sph_integrate.hip", "sph_adjoint.hip", "sph_gravity.hip"]
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -542,6 +542,29 @@ sph_status sph_density_backward(const sph_config* cfg, const sph_particles* p, v
                                               c.s));
 }
 
+size_t sph_gravity_workspace_bytes(const sph_config* cfg)
+{
+    if (!config_ok(cfg)) return 0;
+    return gravity_workspace_bytes(make_layout(cfg->n, cfg->ng_max).lcap);
+}
+
+sph_status sph_gravity(const sph_config* cfg, const sph_particles* p,
+                       const sph_gravity_params* gp, void* ws, void* gws, double* gx,
+                       double* gy, double* gz, sph_stream stream)
+{
+    Ctx c;
+    sph_status st = prepare(cfg, ws, stream, c);
+    if (st) return st;
+    if (!gws || ((uintptr_t)gws & 255)) return SPH_E_WORKSPACE;
+    if (!p || !p->x || !p->y || !p->z || !p->m || !gx || !gy || !gz || !gp) return SPH_E_ARG;
+    if (cfg->periodic[0] || cfg->periodic[1] || cfg->periodic[2]) return SPH_E_ARG;
+    if (!(gp->G >= 0.0) || !(gp->eps >= 0.0) || !(gp->theta >= 0.0) || !isfinite(gp->G) ||
+        !isfinite(gp->eps) || !isfinite(gp->theta))
+        return SPH_E_ARG;
+    return hip_status(launch_gravity(c.P, c.W, p, gws, gp->G, gp->eps, gp->theta, gx, gy, gz,
+                                     c.s));
+}
+
 sph_status sph_neighbors_view(const sph_config* cfg, void* ws, const int32_t** nc,
                               const int32_t** ns, const int32_t** list, int32_t* capacity)
 {

@@ -689,6 +689,10 @@ hipError_t launch_clear_domain(const Ws& W, hipStream_t s);
 // reverse mode (frozen structure): the forward stages of the step must have run
 // on W and p (lists, packed positions and records, stage outputs, g->dt)
 size_t adjoint_workspace_bytes(int64_t n);
+size_t gravity_workspace_bytes(int L);
+hipError_t launch_gravity(const Params& P, const Ws& W, const sph_particles* p, void* gws,
+                          double G, double eps, double theta, double* gx, double* gy,
+                          double* gz, hipStream_t s);
 hipError_t launch_step_backward(const Params& P, const Ws& W, const sph_particles* p,
                                 const sph_globals* g, const sph_grads* gout, sph_grads* gin,
                                 void* adj_ws, hipStream_t s);

@@ -147,6 +147,26 @@ def random_periodic(n: int, seed: int, h_lo: float, h_hi: float, sigma_v: float 
 
 
 # the five workloads the benchmark and the parity tests are sized on
+def evrard_sphere(n: int, seed: int = 7, u0: float = 0.05) -> Workload:
+    """Self-gravitating gas sphere of radius 1 and mass 1 with density
+    rho = 1/(2 pi r), at rest (the standard collapse test of SPH codes with
+    gravity): enclosed mass r^2, so r = sqrt(U) for U uniform, with isotropic
+    directions; equal masses 1/n, u = u0, open boundaries.  h starts at 1.44
+    local mean spacings of the number density n/(2 pi r)."""
+    rng = _rng(seed)
+    r = np.sqrt(rng.random(n))
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pos = d * r[:, None]
+    nd = n / (2.0 * np.pi * np.maximum(r, 1e-3))
+    arr = dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(),
+               vx=np.zeros(n), vy=np.zeros(n), vz=np.zeros(n), m=np.full(n, 1.0 / n),
+               u=np.full(n, u0), h=H_GUESS_SPACINGS * nd ** (-1.0 / 3.0),
+               id=np.arange(n, dtype=np.int64))
+    return Workload(f"evrard{n}", arr, base_params(box_lo=(-1.0, -1.0, -1.0),
+                                                    box_hi=(1.0, 1.0, 1.0), periodic=(0, 0, 0)))
+
+
 def c1_lattice() -> Workload:
     return lattice(20, seed=1, sigma_v=0.01)
 

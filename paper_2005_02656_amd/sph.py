@@ -149,6 +149,9 @@ _SIGS = {
                                        C.c_void_p]),
     "sph_status_string": (C.c_char_p, [C.c_int]),
     "sph_step_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_gravity_workspace_bytes": (C.c_size_t, [C.c_void_p]),
+    "sph_gravity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -464,6 +467,42 @@ def density_backward(cfg: Config, parts: Particles, ws: Workspace, aws: AdjointW
                                       C.c_void_p(rho_bar.data_ptr()), C.c_void_p(xb.data_ptr()),
                                       C.c_void_p(yb.data_ptr()), C.c_void_p(zb.data_ptr()),
                                       _stream(stream)), "sph_density_backward")
+
+
+# --------------------------------------------------------------------------- gravity
+class _GravityParams(C.Structure):
+    _fields_ = [("G", C.c_double), ("eps", C.c_double), ("theta", C.c_double)]
+
+
+class GravityWorkspace:
+    """Caller-owned tree storage of sph_gravity (sph_gravity_workspace_bytes)."""
+
+    def __init__(self, cfg: Config, device="cuda"):
+        nbytes = lib().sph_gravity_workspace_bytes(C.byref(cfg.c()))
+        if nbytes == 0:
+            raise SphError(1, "sph_gravity_workspace_bytes (invalid config)")
+        self.raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.raw.data_ptr()) % 256
+        self.buf = self.raw[off:off + nbytes]
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+
+def gravity(cfg: Config, parts: Particles, ws: Workspace, gws: GravityWorkspace, G: float,
+            eps: float, theta: float, out=None, stream=None):
+    """Enqueues sph_gravity on the slot order of the last build_cells; returns
+    (gx, gy, gz) device tensors per slot."""
+    if out is None:
+        out = tuple(torch.empty(cfg.n, dtype=torch.float64, device=parts["x"].device)
+                    for _ in range(3))
+    gp = _GravityParams(float(G), float(eps), float(theta))
+    ps = parts.c()
+    _check(lib().sph_gravity(C.byref(cfg.c()), C.byref(ps), C.byref(gp), ws.ptr, gws.ptr,
+                             *[C.c_void_p(t.data_ptr()) for t in out], _stream(stream)),
+           "sph_gravity")
+    return out
 
 
 SNAP_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "u", "du_m1",
