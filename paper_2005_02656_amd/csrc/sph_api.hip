@@ -60,6 +60,7 @@ Layout make_layout(int64_t n, int ng_max)
     L.tabD = take(sizeof(double2) * SPH_KERNEL_TABLE_MAX);
     L.tabSf = take(sizeof(float2) * SPH_KERNEL_TABLE_MAX);
     L.tabDf = take(sizeof(float2) * SPH_KERNEL_TABLE_MAX);
+    L.flag = take(sizeof(uint8_t) * n);
     L.total = o;
     return L;
 }
@@ -96,6 +97,7 @@ Ws carve(void* ws, const Layout& L)
     W.tabD = (double2*)(b + L.tabD);
     W.tabSf = (float2*)(b + L.tabSf);
     W.tabDf = (float2*)(b + L.tabDf);
+    W.flag = (uint8_t*)(b + L.flag);
     return W;
 }
 

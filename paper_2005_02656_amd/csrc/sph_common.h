@@ -191,6 +191,7 @@ struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
     size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm, mf, mf2;
     size_t tabS, tabD, tabSf, tabDf;
+    size_t flag;
     size_t total;
     int64_t n, nsort_blocks, hist_len, scan_blocks, ncells_cap;
     int lcap, cand_cap;
@@ -219,6 +220,7 @@ struct Ws {
     double* tmp;               // permute scratch (aliases the list area)
     double2 *tabS, *tabD;      // kernel tables (kernel_table > 0), FP64 and FP32
     float2 *tabSf, *tabDf;
+    uint8_t* flag;             // fused step: 2 h left the short reach, 1 a neighbour of one
 };
 Ws carve(void* ws, const Layout& L);
 

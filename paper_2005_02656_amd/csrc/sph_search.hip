@@ -334,18 +334,25 @@ __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __r
 // FP64.  (A wavefront walking the union of its 64 targets' stencils, with
 // scalar or LDS-staged particle loads, tested 2.4x more pairs and ran 1.6-2.1x
 // slower at 64 M particles.)
-template <int kPer, bool kFull>   // bit k of kPer set: axis k periodic
+// kMode: 0 the short-reach pass over every target; at full reach, 1 the
+// targets whose h left the short reach (flag 2), marking every candidate not
+// so flagged (flag 1), then 2 the marked targets (flag 1)
+template <int kPer, int kMode>   // bit k of kPer set: axis k periodic
 __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__ dom,
                                            const CellRange* __restrict__ cells,
                                            const Pos4* __restrict__ p4,
                                            const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-                                           int32_t* __restrict__ cand, double kap, float sc)
+                                           int32_t* __restrict__ cand, double kap, float sc,
+                                           uint8_t* __restrict__ flag)
 {
+    constexpr bool kFull = kMode != 0;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
     if (a >= P.n) return;
+    if (kMode == 1 && flag[a] != 2) return;
+    if (kMode == 2 && flag[a] != 1) return;
     const Domain D = *dom;
     const Pos4 pa = p4[a];
     const Pos4f fa = pf[a];
@@ -382,6 +389,8 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
             const float qr2 = kFull ? q.r2 * sc : q.r2;
             const bool near = __float_as_uint(r2) < max(far2, __float_as_uint(qr2));
             if (near & (b != self)) {
+                // a neighbour of a grown h redoes its own walk at full reach
+                if (kMode == 1 && flag[b] == 0) flag[b] = 1;
                 if (k < cap) {
                     stage[k & 7][t] = b;
                     if ((k & 7) == 7) {
@@ -407,22 +416,23 @@ template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-    int32_t* __restrict__ cand, double kap, float sc)
+    int32_t* __restrict__ cand, double kap, float sc, uint8_t* __restrict__ flag)
 {
-    candidates<kPer, false>(P, dom, cells, p4, pf, nk, cand, kap, sc);
+    candidates<kPer, 0>(P, dom, cells, p4, pf, nk, cand, kap, sc, flag);
 }
-template <int kPer>
+template <int kPer, int kMode>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates_full(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-    int32_t* __restrict__ cand, double kap, float sc)
+    int32_t* __restrict__ cand, double kap, float sc, uint8_t* __restrict__ flag)
 {
     if (dom->refit == 0u) return;
-    candidates<kPer, true>(P, dom, cells, p4, pf, nk, cand, kap, sc);
+    candidates<kPer, kMode>(P, dom, cells, p4, pf, nk, cand, kap, sc, flag);
 }
 
-// the candidate pass for the periodic axes of P
-static void launch_candidates(bool full, const Params& P, const Ws& W, double kap, hipStream_t s)
+// the candidate pass for the periodic axes of P: mode 0 short reach, 1 and 2
+// the full-reach refits (see candidates())
+static void launch_candidates(int mode, const Params& P, const Ws& W, double kap, hipStream_t s)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     // the records hold the squared short reach; the full pass scales it by
@@ -433,12 +443,15 @@ static void launch_candidates(bool full, const Params& P, const Ws& W, double ka
     if ((double)sc < q) sc = nextafterf(sc, INFINITY);
     with_periodic(P, [&](auto per) {
         constexpr int kPer = decltype(per)::value;
-        if (full)
-            k_candidates_full<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
-                                                                    W.nk, W.cand, kap, sc);
+        if (mode == 1)
+            k_candidates_full<kPer, 1><<<grid_xcd(nb), kBlock, 0, s>>>(
+                P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand, kap, sc, W.flag);
+        else if (mode == 2)
+            k_candidates_full<kPer, 2><<<grid_xcd(nb), kBlock, 0, s>>>(
+                P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand, kap, sc, W.flag);
         else
             k_candidates<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
-                                                               W.nk, W.cand, kap, sc);
+                                                               W.nk, W.cand, kap, sc, W.flag);
     });
 }
 
@@ -494,16 +507,17 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
                                               const int32_t* __restrict__ nk,
                                               const int32_t* __restrict__ cand,
                                               const Pos4* __restrict__ p4, double* __restrict__ h,
-                                              double lam)
+                                              double lam, uint8_t* __restrict__ flag, bool full)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     // lanes past the end shadow the last particle with no candidates, so that
-    // both lanes of every pair run the gathers together
+    // both lanes of every pair run the gathers together; in the full-reach pass
+    // only the targets whose h left the short reach (flag 2) are live
     const int64_t a0 = lb * kBlock + threadIdx.x;
-    const bool live = a0 < P.n;
-    const int64_t a = live ? a0 : P.n - 1;
+    const int64_t a = a0 < P.n ? a0 : P.n - 1;
+    const bool live = a0 < P.n && (!full || flag[a] == 2);
     const int odd = threadIdx.x & 1;
     const Pos4 pa = p4[a];
     const double xa = pa.x, ya = pa.y, za = pa.z;
@@ -544,8 +558,10 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
     }
     if (!live) return;
     h[a] = hc;
+    // the short pass flags the targets whose h may have missed candidates
+    // (2) and clears the others (0); the full-reach pass recomputes the former
+    if (!full) flag[a] = over ? 2 : 0;
     if (over) {
-        // this h may have missed candidates; the full-reach pass recomputes it
         atomicOr(&dom->refit, 1u);
     } else {
         check_cell_range(P, dom, hc);
@@ -556,18 +572,18 @@ template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
-    double lam)
+    double lam, uint8_t* __restrict__ flag)
 {
-    update_h_list<kPer, kTab>(P, dom, nk, cand, p4, h, lam);
+    update_h_list<kPer, kTab>(P, dom, nk, cand, p4, h, lam, flag, false);
 }
 template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_NEWTON_ATTR void k_update_h_list_full(
     Params P, Domain* __restrict__ dom, const int32_t* __restrict__ nk,
     const int32_t* __restrict__ cand, const Pos4* __restrict__ p4, double* __restrict__ h,
-    double lam)
+    double lam, uint8_t* __restrict__ flag)
 {
     if (dom->refit == 0u) return;
-    update_h_list<kPer, kTab>(P, dom, nk, cand, p4, h, lam);
+    update_h_list<kPer, kTab>(P, dom, nk, cand, p4, h, lam, flag, true);
 }
 
 // exact lists from the candidates with the final h (same layout as k_find_neighbors)
@@ -716,7 +732,7 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     // short reach first; the full-reach pair runs only if an h left it (the
     // kernels read the device flag and return at once when it is clear)
     const double lam = fmin(kFusedReach, P.kappa);
-    launch_candidates(false, P, W, lam, s);
+    launch_candidates(0, P, W, lam, s);
     mk.at(1, s);
     if (P.newton_iters > 0) {
         with_periodic(P, [&](auto per) {
@@ -724,17 +740,22 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
                 constexpr int kPer = decltype(per)::value;
                 constexpr bool kTab = decltype(tab)::value;
                 k_update_h_list<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
-                    P, W.dom, W.nk, W.cand, W.p4, p->h, lam);
+                    P, W.dom, W.nk, W.cand, W.p4, p->h, lam, W.flag);
             });
         });
         if (lam < P.kappa) {
-            launch_candidates(true, P, W, P.kappa, s);
+            // targets whose h left the short reach walk again at full reach
+            // and mark their candidates, whose symmetric sets may now hold
+            // them; the marked targets walk again too (their own h stands),
+            // then the grown ones redo Newton over their full candidates
+            launch_candidates(1, P, W, P.kappa, s);
+            launch_candidates(2, P, W, P.kappa, s);
             with_periodic(P, [&](auto per) {
                 with_table(P, [&](auto tab) {
                     constexpr int kPer = decltype(per)::value;
                     constexpr bool kTab = decltype(tab)::value;
                     k_update_h_list_full<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
-                        P, W.dom, W.nk, W.cand, W.p4, p->h, P.kappa);
+                        P, W.dom, W.nk, W.cand, W.p4, p->h, P.kappa, W.flag);
                 });
             });
         }

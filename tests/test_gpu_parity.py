@@ -339,7 +339,7 @@ def test_fused_step_short_reach(name):
     a = w.arrays
     if name == "random":
         h1 = oracle.update_h(ocfg, a["x"], a["y"], a["z"], a["h"])
-        assert np.max(h1 / a["h"]) > sph.SHORT_REACH   # the full-reach pass must run
+        assert np.max(h1 / a["h"]) > sph.SHORT_REACH   # the full-reach refit must run
     r = Run(w, cfg)
     sph.step(cfg, r.parts, r.g, r.ws)
     assert r.status() == (0, 0)
@@ -349,6 +349,40 @@ def test_fused_step_short_reach(name):
     nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, a["x"], a["y"], a["z"], h_o)
     assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
     assert np.array_equal(P, oracle_pairs(lists, gath))
+
+
+@pytest.mark.parametrize("precision", [sph.FP64, sph.MIXED])
+def test_fused_step_partial_refit(precision):
+    """A few targets whose h leaves the short reach: they and the targets within
+    their full reach walk again (and they redo Newton); everyone else keeps its
+    short-reach candidates.  h and the lists are the oracle's exactly, and only
+    part of the candidate counts grow."""
+    w = inputs.lattice(12, seed=1, sigma_v=0.01)
+    cfg, ocfg = configs(w, ng_max=NG, precision=precision)
+    a = dict(w.arrays)
+    a["h"] = oracle.initial_h(ocfg, a)
+    rng = np.random.default_rng(8)
+    few = rng.choice(w.n, 5, replace=False)
+    a["h"][few] *= 0.8
+    h1 = oracle.update_h(ocfg, a["x"], a["y"], a["z"], a["h"])
+    assert np.all(h1[few] / a["h"][few] > sph.SHORT_REACH)
+    rest = np.setdiff1d(np.arange(w.n), few)
+    assert np.all(h1[rest] / a["h"][rest] < sph.SHORT_REACH)
+    r = Run(w, cfg, a)
+    sph.step(cfg, r.parts, r.g, r.ws)
+    assert r.status() == (0, 0)
+    assert rel_err(r.by_id("h"), h1) < TOL
+    P, nc, ns = r.neighbor_pairs()
+    nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, a["x"], a["y"], a["z"], h1)
+    assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
+    assert np.array_equal(P, oracle_pairs(lists, gath))
+    nk_v, _ = sph.candidates_view(cfg, r.ws)
+    nk = np.empty(w.n, np.int64)
+    nk[r.ids()] = nk_v.cpu().numpy()
+    full = nk > np.median(nk)
+    assert full[few].all() and 5 < full.sum() < w.n, full.sum()
+    rho_o = oracle.density(ocfg, a["x"], a["y"], a["z"], h1, a["m"], a["u"])[0]
+    assert rel_err(r.by_id("rho"), rho_o) < (TOL if precision == sph.FP64 else 1e-5)
 
 
 def _reach_counts(w, h0, factors):
@@ -375,8 +409,8 @@ def test_fused_candidates_cover_reach(name):
     """The candidate walk of the fused step tests in FP32 with a widened reach:
     its count for every target lies between the exact number of b != a with
     r_ab < 2 lam max(h0_a, h0_b) and that number at a reach larger by a relative
-    1e-3, for lam the short reach (sph.SHORT_REACH) or, when the full-reach pass
-    ran, kappa."""
+    1e-3, for lam the short reach (sph.SHORT_REACH) or, for the targets the
+    full-reach refit walked again, kappa."""
     w = CASES[name]()
     cfg, _ = configs(w, ng_max=NG)
     r = Run(w, cfg, _with_rho_ref(w))
@@ -389,8 +423,10 @@ def test_fused_candidates_cover_reach(name):
     lams = sorted({min(sph.SHORT_REACH, cfg.h_ratio_max), cfg.h_ratio_max})
     fs = [2 * l for l in lams] + [2 * l * (1 + 1e-3) for l in lams]
     cnt = _reach_counts(w, w.arrays["h"], fs)
-    ok = [bool(np.all((cnt[2 * l] <= nk) & (nk <= cnt[2 * l * (1 + 1e-3)]))) for l in lams]
-    assert any(ok), name
+    ok = np.zeros(w.n, bool)
+    for l in lams:
+        ok |= (cnt[2 * l] <= nk) & (nk <= cnt[2 * l * (1 + 1e-3)])
+    assert np.all(ok), name
 
 
 @pytest.mark.parametrize("uniform", [False, True])
