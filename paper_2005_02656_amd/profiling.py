@@ -1,15 +1,19 @@
 """Summaries of rocprofv3 output for the kernels of one workload.
 
     python -m paper_2005_02656_amd.profiling --trace DIR [--fetch DIR --write DIR
-        --calib-bytes N] --kernel k_candidates --workload c4 --command "..." --out FILE
+        --calib-bytes N] [--l2 DIR] [--sq DIR] --kernel k_candidates --workload c4
+        --command "..." --out FILE
 
 Reads the CSV output of `rocprofv3 --kernel-trace --stats` (per-kernel call
-counts and durations) and, optionally, of two `rocprofv3 --pmc FETCH_SIZE` and
-`--pmc WRITE_SIZE` runs of the same command.  The byte counters are scaled by
-what they read for a device copy of known size in the same run (the runtime's
-copy kernel), per counter, and reported per launch.  The summary records a
-digest of the library sources so that a reader (bench.py) can tell whether the
-counters still describe the kernels that are built.
+counts and durations) and, optionally, of `rocprofv3 --pmc` runs of the same
+command: FETCH_SIZE and WRITE_SIZE (HBM bytes), TCC_HIT_sum and TCC_MISS_sum
+(L2 hit rate), and SQ_INSTS_VALU, SQ_INSTS_VALU_FLOPS_FP64,
+SQ_INSTS_VALU_FLOPS_FP32, SQ_WAVES, VALUBusy and OccupancyPercent (vector
+instructions, counted flops, VALU busy and occupancy).  The byte counters are
+scaled by what they read for a device copy of known size in the same run (the
+runtime's copy kernel), per counter, and reported per launch.  The summary
+records a digest of the library sources so that a reader (bench.py) can tell
+whether the counters still describe the kernels that are built.
 """
 from __future__ import annotations
 
@@ -111,6 +115,45 @@ def summary(args) -> str:
         if args.kernel in fb:
             lines += ["", f"fetch_bytes_per_launch: {fb[args.kernel]:.6e}",
                       f"write_bytes_per_launch: {wb.get(args.kernel, 0.0):.6e}"]
+    kern_rows = [t[0] for t in st if t[0].startswith("k_")][:args.top]
+    if args.l2:
+        hit, miss = counter_means(args.l2, "TCC_HIT_sum"), counter_means(args.l2, "TCC_MISS_sum")
+        lines += ["", "## L2 (rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum)", "",
+                  "| kernel | hit rate | requests per launch |", "|---|---|---|"]
+        for k in kern_rows:
+            if k in hit and k in miss:
+                h, mi = statistics.fmean(hit[k]), statistics.fmean(miss[k])
+                lines.append(f"| {k} | {h / max(h + mi, 1):.3f} | {h + mi:.4e} |")
+        if args.kernel in hit and args.kernel in miss:
+            h, mi = statistics.fmean(hit[args.kernel]), statistics.fmean(miss[args.kernel])
+            lines += ["", f"l2_hit_rate: {h / max(h + mi, 1):.4f}"]
+    if args.sq:
+        cs = {c: counter_means(args.sq, c) for c in
+              ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32",
+               "SQ_WAVES", "VALUBusy", "OccupancyPercent")}
+        lines += ["", "## Vector ALU (rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_VALU_FLOPS_FP64 "
+                  "SQ_INSTS_VALU_FLOPS_FP32 SQ_WAVES VALUBusy OccupancyPercent)", "",
+                  "| kernel | VALU insts per wave | FP64 flops per launch | FP32 flops per launch "
+                  "| VALU busy % | occupancy % |", "|---|---|---|---|---|---|"]
+        mean = lambda c, k: statistics.fmean(cs[c][k]) if k in cs[c] else float("nan")
+        for k in kern_rows:
+            if k not in cs["SQ_INSTS_VALU"]:
+                continue
+            w = mean("SQ_WAVES", k)
+            lines.append(f"| {k} | {mean('SQ_INSTS_VALU', k) / max(w, 1):.0f} | "
+                         f"{mean('SQ_INSTS_VALU_FLOPS_FP64', k):.4e} | "
+                         f"{mean('SQ_INSTS_VALU_FLOPS_FP32', k):.4e} | "
+                         f"{mean('VALUBusy', k):.1f} | {mean('OccupancyPercent', k):.1f} |")
+        k = args.kernel
+        if k in cs["SQ_INSTS_VALU"]:
+            # the FLOPS counters count each wavefront instruction once: times
+            # the 64 lanes they are lane flops (k_integrate: 56 per particle,
+            # its arithmetic counted by hand)
+            lines += ["", f"valu_insts_per_wave: {mean('SQ_INSTS_VALU', k) / max(mean('SQ_WAVES', k), 1):.1f}",
+                      f"fp64_flops_per_launch: {mean('SQ_INSTS_VALU_FLOPS_FP64', k):.6e}",
+                      f"fp64_lane_flops_per_launch: {64 * mean('SQ_INSTS_VALU_FLOPS_FP64', k):.6e}",
+                      f"valu_busy_percent: {mean('VALUBusy', k):.2f}",
+                      f"occupancy_percent: {mean('OccupancyPercent', k):.2f}"]
     return "\n".join(lines) + "\n"
 
 
@@ -132,6 +175,8 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--calib-bytes", type=int, default=0)
+    ap.add_argument("--l2", help="rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum output")
+    ap.add_argument("--sq", help="rocprofv3 --pmc SQ_INSTS_VALU ... OccupancyPercent output")
     ap.add_argument("--kernel", required=True)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--command", required=True)
