@@ -130,10 +130,14 @@ def traffic_from_profile(kernel, workload):
 
 
 def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload, fused, urec=False):
-    """Roofline of the phase that takes the longest.  Both ceilings are evaluated
+    """Roofline of the phase that takes the longest among those the method's
+    own work is counted for (the candidate walk of the fused search has none:
+    its tests depend on the cell structure).  Both ceilings are evaluated
     (algorithmic HBM bytes against 8 TB/s, algorithmic FP64 flops against the
     78.6 TFLOP/s vector peak); the binding one (larger fraction) is reported."""
-    dom = max(phases, key=phases.get)
+    counted = [k for k in phases
+               if bytes_per_particle(k, k_g, k_s, wc, k_c, iters, fused, urec) > 0]
+    dom = max(counted, key=phases.get)
     t = phases[dom] * 1e-3
     by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters, fused, urec)
     hbm = by * n / t / 1e9

@@ -63,6 +63,10 @@ def test_roofline_reports_the_binding_ceiling():
     r2 = bench.roofline({"build_cells": 50.0, "integrate": 1.0}, n, k_g, k_s, True, 2, k_c,
                         "c4", True)
     assert r2["bound"] == "hbm" and "alt" not in r2
+    # the candidate walk has no algorithmic count: a longer walk is passed over
+    r4 = bench.roofline({**phases, "candidates": 100.0}, n, k_g, k_s, True, 2, k_c,
+                        "no-such-workload", True)
+    assert r4["phase"] == "momentum_energy"
     # with equal masses and sound speeds the momentum phase runs its own kernel
     r3 = bench.roofline(phases, n, k_g, k_s, True, 2, k_c, "c4", True, urec=True)
     assert r3["kernel"] == "k_momentum_energy_u"
