@@ -97,8 +97,11 @@ def _cc(cfg: Config) -> _CConfig:
 def lib():
     global _lib
     if _lib is None:
-        path = _build.library_path()
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SOURCE):
+        # SPH_ORACLE_LIBRARY: another build of the oracle (the sanitizer build)
+        path = os.environ.get("SPH_ORACLE_LIBRARY") or _build.library_path()
+        if not os.environ.get("SPH_ORACLE_LIBRARY") and (
+                not os.path.exists(path) or
+                os.path.getmtime(path) < os.path.getmtime(_build.SOURCE)):
             _build.build()
         _lib = C.CDLL(path)
         d, i64, vp = C.c_double, C.c_int64, C.c_void_p

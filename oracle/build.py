@@ -11,12 +11,17 @@ def library_path() -> str:
     return os.path.join(BUILD_DIR, "libsph_oracle.so")
 
 
-def build() -> str:
+def build(out: str = None, sanitize: bool = False) -> str:
+    """Compiles the oracle; sanitize=True adds the host AddressSanitizer and
+    UndefinedBehaviorSanitizer (the loading process must preload libasan)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    out = library_path()
+    out = out or library_path()
     tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", SOURCE, "-o", tmp, "-lm"]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                    "-fno-omit-frame-pointer", "-g"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
