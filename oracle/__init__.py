@@ -308,20 +308,31 @@ def key_domain(cfg, x, y, z, h):
     return lo, hi
 
 
-def sort_keys(keys):
+def sort_keys(keys, level=None):
+    """Stable order of the keys (ties by index); with level L only their prefix
+    of L levels (3L bits) is compared: the particle order of the cell build,
+    whose finest cell level is leaf_level(n)."""
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     perm = np.zeros(keys.size, np.int64)
-    lib().ora_sort_keys(C.c_int64(keys.size), _p(keys), _p(perm))
+    if level is None:
+        lib().ora_sort_keys(C.c_int64(keys.size), _p(keys), _p(perm))
+    else:
+        lib().ora_sort_keys_level(C.c_int64(keys.size), _p(keys), C.c_int(int(level)),
+                                  _p(perm))
     return perm
 
 
 # --------------------------------------------------------------------------- gravity
-def gravity_leaf_level(n: int) -> int:
-    """Deepest level L of the gravity tree: the largest L <= 9 with 8^L <= n."""
+def leaf_level(n: int) -> int:
+    """Finest cell level L of n particles (the particle order's and the gravity
+    tree's): the largest L <= 9 with 8^L <= n."""
     L = 0
     while L < 9 and 8 ** (L + 1) <= max(n, 1):
         L += 1
     return L
+
+
+gravity_leaf_level = leaf_level
 
 
 def gravity_direct(x, y, z, m, G, eps, targets=None):

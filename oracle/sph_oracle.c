@@ -666,22 +666,40 @@ void ora_bbox(int64_t n, const double* x, const double* y, const double* z,
     memcpy(out, o, sizeof o);
 }
 
-/* stable ordering of keys: perm[i] = index of the i-th smallest key, ties by index */
+/* stable ordering of keys: perm[i] = index of the i-th smallest key, ties by
+ * index.  Only the key's prefix above bit g_sort_shift is compared: the depth
+ * first order of the octree down to a given level, particles in one cell of
+ * that level keeping the order they came in (section 4.3 orders the particles
+ * by the tree; it leaves the order inside the finest cells open). */
 static const uint64_t* g_sort_keys;
+static int g_sort_shift;
 static int ora_key_cmp(const void* pa, const void* pb)
 {
     int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
-    uint64_t ka = g_sort_keys[a], kb = g_sort_keys[b];
+    uint64_t ka = g_sort_keys[a] >> g_sort_shift, kb = g_sort_keys[b] >> g_sort_shift;
     if (ka != kb) return ka < kb ? -1 : 1;
     return (a > b) - (a < b);
 }
 
-void ora_sort_keys(int64_t n, const uint64_t* keys, int64_t* perm)
+static void ora_sort_by(int64_t n, const uint64_t* keys, int shift, int64_t* perm)
 {
     for (int64_t i = 0; i < n; ++i) perm[i] = i;
     g_sort_keys = keys;
+    g_sort_shift = shift;
     qsort(perm, (size_t)n, sizeof(int64_t), ora_key_cmp);
     g_sort_keys = NULL;
+}
+
+/* the whole 63-bit key */
+void ora_sort_keys(int64_t n, const uint64_t* keys, int64_t* perm)
+{
+    ora_sort_by(n, keys, 0, perm);
+}
+
+/* the prefix of L levels (3L bits) */
+void ora_sort_keys_level(int64_t n, const uint64_t* keys, int L, int64_t* perm)
+{
+    ora_sort_by(n, keys, 3 * (21 - L), perm);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -773,8 +791,8 @@ void ora_multipole_accel(const double* mo, const double* x, double G, double eps
         g[k] = -G * mo[0] * r[k] * ir3 + G * (Qr[k] * ir5 - 2.5 * rQr * r[k] * ir7);
 }
 
-/* The tree: the particles in the stable order of their keys (key domain lo/hi
- * as ora_morton_keys); the node of level l (0..L) with prefix P holds the
+/* The tree: the particles in the stable order of their keys' prefix of L
+ * levels (key domain lo/hi as ora_morton_keys); the node of level l (0..L) with prefix P holds the
  * particles whose key shifted right by 3(21-l) equals P; its size is the
  * largest extent of the key domain over 2^l.  Walk per target, depth first
  * from the root, children in ascending prefix:
@@ -851,7 +869,7 @@ void ora_gravity_tree(int64_t n, const double* x, const double* y, const double*
     int64_t* order = malloc(sizeof(int64_t) * n);
     uint64_t* skeys = malloc(sizeof(uint64_t) * n);
     ora_morton_keys(n, x, y, z, lo, hi, keys);
-    ora_sort_keys(n, keys, order);
+    ora_sort_keys_level(n, keys, L, order);
     for (int64_t i = 0; i < n; ++i) skeys[i] = keys[order[i]];
     ora_gtree T;
     T.L = L;

@@ -442,6 +442,18 @@ __global__ __launch_bounds__(kBlock) void k_fill_tables(Params P, double2* __res
     tDf[i] = make_float2((float)D[0], (float)D[1]);
 }
 
+__global__ __launch_bounds__(kBlock) void k_copy_sorted(const uint64_t* __restrict__ kin,
+                                                        const uint32_t* __restrict__ iin,
+                                                        uint64_t* __restrict__ kout,
+                                                        uint32_t* __restrict__ iout, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i < n) {
+        kout[i] = kin[i];
+        iout[i] = iin[i];
+    }
+}
+
 hipError_t launch_clear_domain(const Ws& W, hipStream_t s)
 {
     k_clear_domain<<<1, 64, 0, s>>>(W.dom);
@@ -462,13 +474,19 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
     k_domain_end<<<1, 1, 0, s>>>(P, W.dom);
     k_keys<<<nb, kBlock, 0, s>>>(p->x, p->y, p->z, n, W.dom, W.keys0, W.idx0);
 
-    // 8 passes of 8 bits over the 63-bit key; the result ends in keys0/idx0
+    // Stable LSD radix sort by the key's prefix of lcap levels (3 lcap bits, 8
+    // bits a pass): the depth-first order of the octree down to its finest
+    // cells (section 4.3), every cell level the step uses being at most lcap.
+    // Inside a finest cell the particles keep the order they came in, so the
+    // order is updated, not rebuilt: only particles that changed cells move.
+    const int s0 = 3 * (kKeyBits - L.lcap);
+    const int passes = (3 * L.lcap + 7) / 8;
     uint64_t* kin = W.keys0;
     uint64_t* kout = W.keys1;
     uint32_t* iin = W.idx0;
     uint32_t* iout = W.idx1;
-    for (int pass = 0; pass < 8; ++pass) {
-        int shift = 8 * pass;
+    for (int pass = 0; pass < passes; ++pass) {
+        int shift = s0 + 8 * pass;
         k_radix_hist<<<L.nsort_blocks, kBlock, 0, s>>>(kin, n, shift, W.hist, L.nsort_blocks);
         k_scan_reduce<<<L.scan_blocks, kBlock, 0, s>>>(W.hist, L.hist_len, W.scanpart);
         k_scan_top<<<1, kBlock, 0, s>>>(W.scanpart, L.scan_blocks);
@@ -478,6 +496,8 @@ hipError_t launch_build_cells(const Params& P, const Layout& L, const Ws& W,
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* ti = iin; iin = iout; iout = ti;
     }
+    // the sorted keys and order end in keys0/idx0
+    if (kin != W.keys0) k_copy_sorted<<<nb, kBlock, 0, s>>>(kin, iin, W.keys0, W.idx0, n);
 
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
     k_cells_clear<<<cb, kBlock, 0, s>>>(W.dom, W.cells, L.ncells_cap);

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_uniform_check(int64_t n, const doubl
     if (__ballot(diff) && (threadIdx.x & 63) == 0) atomicOr(&dom->nonuniform, 1u);
 }
 
-template <bool kTab>
+template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Params P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ list,
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_IAD) void k_iad(Par
 #endif
             if (!ok[u]) continue;
             double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
+            double r2 = disp_p<kPer>(P, xa, ya, za, q[u].x, q[u].y, q[u].z, dx, dy, dz);
             double s = q[u].v * (w0 * kern_S_t<kTab>(P, r2 * tsc));
             t11 += s * dx * dx;
             t12 += s * dx * dy;
@@ -283,7 +283,7 @@ SPH_DEV double nbr_m(const MomNbr& r, double) { return r.m; }
 SPH_DEV double nbr_c(const MomNbr& r, double) { return r.c; }
 SPH_DEV double nbr_m(const MomNbrU&, double m0) { return m0; }
 SPH_DEV double nbr_c(const MomNbrU&, double c0) { return c0; }
-template <class Rec, int kMomBatch, bool kTab>
+template <class Rec, int kMomBatch, int kPer, bool kTab>
 __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restrict__ dom,
                                                 const int32_t* __restrict__ nc,
                                                 const int32_t* __restrict__ ns,
@@ -327,7 +327,7 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
 #pragma clang fp contract(fast)
 #endif
             double dx, dy, dz;
-            double r2 = disp(P, xa, ya, za, rb.x, rb.y, rb.z, dx, dy, dz);
+            double r2 = disp_p<kPer>(P, xa, ya, za, rb.x, rb.y, rb.z, dx, dy, dz);
             double Wa = 0.0;
             if (gather) Wa = w0a * kern_S_t<kTab>(P, r2 * tsa);
             // W(r, h_b) on its support t_b < pi^2 (v_b < 2)
@@ -412,7 +412,7 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
 // third wavefront per SIMD with batches of 3 (52.7 ms against 54.9 at two
 // wavefronts and batches of 4, 64 M particles); the 144-byte records spill
 // at three.
-template <bool kTab>
+template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
@@ -427,10 +427,10 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params 
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
-    momentum_energy<MomNbr, SPH_MOM_BATCH, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
+    momentum_energy<MomNbr, SPH_MOM_BATCH, kPer, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
 }
 
-template <bool kTab>
+template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_MOM_U_ATTR void k_momentum_energy_u(Params P, Domain* __restrict__ dom,
                                                                 const int32_t* __restrict__ nc,
                                                                 const int32_t* __restrict__ ns,
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kBlock) SPH_MOM_U_ATTR void k_momentum_energy_u(Par
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
-    momentum_energy<MomNbrU, SPH_MOM_U_BATCH, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
+    momentum_energy<MomNbrU, SPH_MOM_U_BATCH, kPer, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
 }
 
 __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals* g)
@@ -490,10 +490,12 @@ hipError_t launch_iad(const Params& P, const Layout& L, const Ws& W, sph_particl
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     k_volume<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.p4, W.vol, W.pv);
     if (write_rec) launch_uniform_check(P, W, p, s);
-    with_table(P, [&](auto tab) {
-        k_iad<decltype(tab)::value><<<grid_xcd(nb), kBlock, 0, s>>>(
-            P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12, p->c13, p->c22, p->c23, p->c33,
-            rec_src(p), write_rec ? (void*)W.rec : nullptr);
+    with_periodic(P, [&](auto per) {
+        with_table(P, [&](auto tab) {
+            k_iad<decltype(per)::value, decltype(tab)::value><<<grid_xcd(nb), kBlock, 0, s>>>(
+                P, W.dom, W.nc, W.list, W.p4, W.pv, p->c11, p->c12, p->c13, p->c22, p->c23,
+                p->c33, rec_src(p), write_rec ? (void*)W.rec : nullptr);
+        });
     });
     return hipGetLastError();
 }
@@ -530,12 +532,15 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
     MomSelf T{p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p,
               p->h, p->m, p->c};
     k_dtmin_begin<<<1, 1, 0, s>>>(W.dom);
-    with_table(P, [&](auto tab) {
-        constexpr bool kTab = decltype(tab)::value;
-        k_momentum_energy_u<kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
-            P, W.dom, W.nc, W.ns, W.list, (const MomNbrU*)W.rec, T, p->u, O);
-        k_momentum_energy<kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
-            P, W.dom, W.nc, W.ns, W.list, (const MomNbr*)W.rec, T, p->u, O);
+    with_periodic(P, [&](auto per) {
+        with_table(P, [&](auto tab) {
+            constexpr int kPer = decltype(per)::value;
+            constexpr bool kTab = decltype(tab)::value;
+            k_momentum_energy_u<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+                P, W.dom, W.nc, W.ns, W.list, (const MomNbrU*)W.rec, T, p->u, O);
+            k_momentum_energy<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
+                P, W.dom, W.nc, W.ns, W.list, (const MomNbr*)W.rec, T, p->u, O);
+        });
     });
     return hipGetLastError();
 }

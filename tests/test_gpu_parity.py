@@ -65,7 +65,7 @@ def test_build_cells_order(case):
     a = w.arrays
     lo, hi = oracle.key_domain(ocfg, a["x"], a["y"], a["z"], a["h"])
     keys_o = oracle.morton_keys(a["x"], a["y"], a["z"], lo, hi)
-    perm_o = oracle.sort_keys(keys_o)
+    perm_o = oracle.sort_keys(keys_o, level=oracle.leaf_level(w.n))
     assert np.array_equal(keys_g, keys_o[perm_o])
     assert np.array_equal(perm_g.astype(np.int64), perm_o)
     assert np.array_equal(r.ids(), perm_o)

@@ -44,3 +44,16 @@ def test_stable_sort(ora):
     keys = np.array([5, 3, 5, 1, 3, 5, 0], dtype=np.uint64)
     perm = ora.sort_keys(keys)
     assert list(perm) == [6, 3, 1, 4, 0, 2, 5]
+
+
+def test_level_order_is_a_stable_prefix_sort(ora):
+    """The particle order of the cell build: a stable sort by the keys' prefix of
+    L levels (numpy's stable argsort of key >> 3(21 - L)); at L = 21 it is the
+    full-key order, and inside one finest cell the input order survives."""
+    rng = np.random.default_rng(4)
+    keys = rng.integers(0, 1 << 63, 5000, dtype=np.uint64)
+    keys[1000:1100] = keys[50]          # ties
+    for L in (0, 1, 3, 7, 8, 9, 21):
+        want = np.argsort(keys >> np.uint64(3 * (21 - L)), kind="stable")
+        assert np.array_equal(ora.sort_keys(keys, level=L), want), L
+    assert np.array_equal(ora.sort_keys(keys, level=21), ora.sort_keys(keys))
