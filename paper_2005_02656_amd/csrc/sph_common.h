@@ -554,7 +554,7 @@ inline void with_table(const Params& P, F&& f)
 #define SPH_MOM_ATTR SPH_WAVES_CAP(SPH_WAVES_MOM)
 #endif
 #ifndef SPH_MOM_U_ATTR
-#define SPH_MOM_U_ATTR SPH_WAVES_EXACT(3)
+#define SPH_MOM_U_ATTR SPH_WAVES_EXACT(2)
 #endif
 #ifndef SPH_WAVES_CAND
 #define SPH_WAVES_CAND 7
@@ -607,9 +607,10 @@ SPH_DEV void finish_density(const Params& P, Domain* dom, const DensOut& O, int6
 #ifndef SPH_MOM_BATCH
 #define SPH_MOM_BATCH 4
 #endif
-// the momentum pass over 112-byte records: batches of 3 at three wavefronts
+// the momentum pass over 112-byte records, staged through LDS: batches of 2
+// at two wavefronts (57 KB of LDS per workgroup)
 #ifndef SPH_MOM_U_BATCH
-#define SPH_MOM_U_BATCH 3
+#define SPH_MOM_U_BATCH 2
 #endif
 
 // neighbour loops load this many neighbours' records before computing on them

@@ -290,10 +290,14 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
                                                 const int32_t* __restrict__ list,
                                                 const Rec* __restrict__ rec, const MomSelf& T,
                                                 const double* __restrict__ u, const MomOut& O,
-                                                int64_t a)
+                                                int64_t a_lane)
 {
+    // lanes past the end shadow the last slot with an empty list (every lane
+    // of a wavefront takes part in the staged gathers)
+    const bool live = a_lane < P.n;
+    const int64_t a = live ? a_lane : P.n - 1;
     double dtc = INFINITY;
-    if (a < P.n) {
+    {
         const Rec ra = rec[a];
         const double m0 = T.m[0], c0 = T.c[0];
         const double xa = ra.x, ya = ra.y, za = ra.z, ha = T.h[a];
@@ -307,8 +311,8 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
         const double w0a = P.bn / (ha * ha * ha);
         const double al = P.alpha;
         const int ng = P.ng_max;
-        const int cg = min(nc[a], ng);
-        const int co = min(ns[a] - nc[a], ng);
+        const int cg = live ? min(nc[a], ng) : 0;
+        const int co = live ? min(ns[a] - nc[a], ng) : 0;
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
         // list entries of the batch starting at k0 (-1 past the end)
@@ -369,36 +373,82 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
         // the target itself and are skipped)
         int32_t nx[kMomBatch];
         entries(0, nx);
-        for (int k0 = 0; k0 < total; k0 += kMomBatch) {
-            bool ok[kMomBatch];
-            Rec rb[kMomBatch];
+        if constexpr (sizeof(Rec) == sizeof(MomNbrU)) {
+            // Staged gathers (the 112-byte records): each lane's loads of its
+            // own neighbour's record fetch seven columns from seven places.
+            // Instead the wavefront loads the 64 records of a batch step
+            // together, lane L taking column (64 i + L) mod 7 of record
+            // (64 i + L) / 7 in load i, so that each load covers nine whole
+            // records; the columns go to LDS in record order and every lane
+            // then reads its own record (a stride of 28 dwords: no bank
+            // conflicts).  C4: 52.4 -> 48.9 ms.
+            constexpr int kCols = (int)(sizeof(Rec) / 16);
+            static_assert(sizeof(Rec) % 16 == 0, "records of whole 16-byte columns");
+            __shared__ int4 stage[kBlock / 64][kMomBatch][64 * kCols];
+            const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+            int tmax = total;   // the wavefront runs to its longest list
+            for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
+            const int4* col = (const int4*)rec;
+            for (int k0 = 0; k0 < tmax; k0 += kMomBatch) {
+                bool ok[kMomBatch];
 #pragma unroll
-            for (int u = 0; u < kMomBatch; ++u) {
-                ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
-                rb[u] = rec[ok[u] ? nx[u] : (int32_t)a];
+                for (int u = 0; u < kMomBatch; ++u) {
+                    ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+                    const int32_t src = ok[u] ? nx[u] : (int32_t)a;
+#pragma unroll
+                    for (int i = 0; i < kCols; ++i) {
+                        const int q = 64 * i + lane;
+                        const int r = q / kCols;
+                        const int32_t b = __shfl(src, r, 64);
+                        stage[wv][u][q] = col[(int64_t)b * kCols + (q - r * kCols)];
+                    }
+                }
+                entries(k0 + kMomBatch, nx);
+                // LDS operations of one wavefront complete in order; the fences
+                // keep the compiler from moving the reads above the writes or
+                // the next batch's writes above this batch's reads
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+                for (int u = 0; u < kMomBatch; ++u) {
+                    const Rec rb = *(const Rec*)&stage[wv][u][lane * kCols];
+                    if (ok[u]) pair(k0 + u < cg, rb);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
-            entries(k0 + kMomBatch, nx);
+        } else {
+            for (int k0 = 0; k0 < total; k0 += kMomBatch) {
+                bool ok[kMomBatch];
+                Rec rb[kMomBatch];
 #pragma unroll
-            for (int u = 0; u < kMomBatch; ++u)
-                if (ok[u]) pair(k0 + u < cg, rb[u]);
+                for (int u = 0; u < kMomBatch; ++u) {
+                    ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+                    rb[u] = rec[ok[u] ? nx[u] : (int32_t)a];
+                }
+                entries(k0 + kMomBatch, nx);
+#pragma unroll
+                for (int u = 0; u < kMomBatch; ++u)
+                    if (ok[u]) pair(k0 + u < cg, rb[u]);
+            }
         }
         const double du = pa_ * e1 + 0.5 * e2;
-        O.ax[a] = axs;
-        O.ay[a] = ays;
-        O.az[a] = azs;
-        O.du[a] = du;
-        if (!isfinite(axs) || !isfinite(ays) || !isfinite(azs) || !isfinite(du))
-            set_err(dom, SPH_ERRBIT_NONFINITE);
-        // time-step candidate: Courant, acceleration and energy criteria
-        dtc = P.courant * (ha / ca);
-        if (P.acc_dt > 0.0) {
-            double am = sqrt((axs * axs + ays * ays) + azs * azs);
-            double qa = P.acc_dt * sqrt(ha / am);
-            if (qa < dtc) dtc = qa;
-        }
-        if (P.energy_dt > 0.0) {
-            double qu = P.energy_dt * (fabs(u[a]) / fabs(du));
-            if (qu < dtc) dtc = qu;
+        if (live) {
+            O.ax[a] = axs;
+            O.ay[a] = ays;
+            O.az[a] = azs;
+            O.du[a] = du;
+            if (!isfinite(axs) || !isfinite(ays) || !isfinite(azs) || !isfinite(du))
+                set_err(dom, SPH_ERRBIT_NONFINITE);
+            // time-step candidate: Courant, acceleration and energy criteria
+            dtc = P.courant * (ha / ca);
+            if (P.acc_dt > 0.0) {
+                double am = sqrt((axs * axs + ays * ays) + azs * azs);
+                double qa = P.acc_dt * sqrt(ha / am);
+                if (qa < dtc) dtc = qa;
+            }
+            if (P.energy_dt > 0.0) {
+                double qu = P.energy_dt * (fabs(u[a]) / fabs(du));
+                if (qu < dtc) dtc = qu;
+            }
         }
     }
     // wavefront minimum of the candidates, then the global one
@@ -408,10 +458,11 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
 }
 
 // One kernel per record layout; both are launched and the one the uniformity
-// flag did not select returns at once.  The 112-byte records leave room for a
-// third wavefront per SIMD with batches of 3 (52.7 ms against 54.9 at two
-// wavefronts and batches of 4, 64 M particles); the 144-byte records spill
-// at three.
+// flag did not select returns at once.  The 144-byte records gather per lane in
+// batches of 4 at two wavefronts per SIMD (they spill at three); the 112-byte
+// records are staged through LDS in batches of 2 at two wavefronts (at 64 M
+// particles 48.9 ms; per-lane gathers took 52.4 ms at three wavefronts and
+// batches of 3, 54.9 at two and batches of 4).
 template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,

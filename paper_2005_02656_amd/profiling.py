@@ -1,17 +1,21 @@
 """Summaries of rocprofv3 output for the kernels of one workload.
 
     python -m paper_2005_02656_amd.profiling --trace DIR [--fetch DIR --write DIR
-        --calib-bytes N] [--l2 DIR] [--sq DIR] --kernel k_candidates --workload c4
-        --command "..." --out FILE
+        --calib-bytes N] [--l2 DIR] [--sq DIR] [--mem DIR] --kernel k_candidates
+        --workload c4 --command "..." --out FILE
 
 Reads the CSV output of `rocprofv3 --kernel-trace --stats` (per-kernel call
 counts and durations) and, optionally, of `rocprofv3 --pmc` runs of the same
 command: FETCH_SIZE and WRITE_SIZE (HBM bytes), TCC_HIT_sum and TCC_MISS_sum
 (L2 hit rate), and SQ_INSTS_VALU, SQ_INSTS_VALU_FLOPS_FP64,
 SQ_INSTS_VALU_FLOPS_FP32, SQ_WAVES, VALUBusy and OccupancyPercent (vector
-instructions, counted flops, VALU busy and occupancy).  The byte counters are
-scaled by what they read for a device copy of known size in the same run (the
-runtime's copy kernel), per counter, and reported per launch.  The summary
+instructions, counted flops, VALU busy and occupancy), and the L1/address
+path: TA_BUSY_avr, TA_ADDR_STALLED_BY_TC_CYCLES_sum, TCP_TOTAL_CACHE_ACCESSES_sum,
+TCP_TCC_READ_REQ_sum, TCP_TCC_READ_REQ_LATENCY_sum and GRBM_GUI_ACTIVE (how busy
+the texture addresser is, the L1 hit rate and the L2 latency the L1 sees).
+The byte counters are scaled by what they read for a device copy of known size
+in the same run (the runtime's copy kernel), per counter, and reported per
+launch.  The summary
 records a digest of the library sources so that a reader (bench.py) can tell
 whether the counters still describe the kernels that are built.
 """
@@ -55,6 +59,15 @@ def _one(pattern):
     if not got:
         raise FileNotFoundError(pattern)
     return got[0]
+
+
+# the L1/address-path pass: 2 TA, 4 TCP and 1 GRBM counters fit one run.
+# GRBM_GUI_ACTIVE comes summed over the chip's 8 XCDs (8 times the kernel's
+# clock cycles); TA_BUSY_avr is per TA (one per CU) and the _sum counters add
+# the 256 CUs' values.
+XCDS, CUS = 8, 256
+MEM_COUNTERS = ("TA_BUSY_avr", "TA_ADDR_STALLED_BY_TC_CYCLES_sum", "TCP_TOTAL_CACHE_ACCESSES_sum",
+                "TCP_TCC_READ_REQ_sum", "TCP_TCC_READ_REQ_LATENCY_sum", "GRBM_GUI_ACTIVE")
 
 
 def kernel_stats(trace_dir: str) -> list:
@@ -154,6 +167,32 @@ def summary(args) -> str:
                       f"fp64_lane_flops_per_launch: {64 * mean('SQ_INSTS_VALU_FLOPS_FP64', k):.6e}",
                       f"valu_busy_percent: {mean('VALUBusy', k):.2f}",
                       f"occupancy_percent: {mean('OccupancyPercent', k):.2f}"]
+    if args.mem:
+        cs = {c: counter_means(args.mem, c) for c in MEM_COUNTERS}
+        lines += ["", "## L1 and address path (rocprofv3 --pmc " + " ".join(MEM_COUNTERS) + ")",
+                  "", "| kernel | TA busy % | TA stalled by L1 % | L1 hit rate | "
+                  "L1 accesses per launch | L1 to L2 reads per launch | L2 read latency (cycles) |",
+                  "|---|---|---|---|---|---|---|"]
+        mean = lambda c, k: statistics.fmean(cs[c][k]) if k in cs[c] else float("nan")
+        for k in kern_rows:
+            if k not in cs["GRBM_GUI_ACTIVE"]:
+                continue
+            cyc = max(mean("GRBM_GUI_ACTIVE", k) / XCDS, 1.0)
+            acc, req = mean("TCP_TOTAL_CACHE_ACCESSES_sum", k), mean("TCP_TCC_READ_REQ_sum", k)
+            lines.append(f"| {k} | {100 * mean('TA_BUSY_avr', k) / cyc:.1f} | "
+                         f"{100 * mean('TA_ADDR_STALLED_BY_TC_CYCLES_sum', k) / (CUS * cyc):.1f} | "
+                         f"{1 - req / max(acc, 1):.3f} | {acc:.4e} | {req:.4e} | "
+                         f"{mean('TCP_TCC_READ_REQ_LATENCY_sum', k) / max(req, 1):.0f} |")
+        k = args.kernel
+        if k in cs["GRBM_GUI_ACTIVE"]:
+            cyc = max(mean("GRBM_GUI_ACTIVE", k) / XCDS, 1.0)
+            acc, req = mean("TCP_TOTAL_CACHE_ACCESSES_sum", k), mean("TCP_TCC_READ_REQ_sum", k)
+            lines += ["", f"ta_busy_percent: {100 * mean('TA_BUSY_avr', k) / cyc:.2f}",
+                      f"ta_stalled_by_l1_percent: "
+                      f"{100 * mean('TA_ADDR_STALLED_BY_TC_CYCLES_sum', k) / (CUS * cyc):.2f}",
+                      f"l1_accesses_per_launch: {acc:.6e}",
+                      f"l1_hit_rate: {1 - req / max(acc, 1):.4f}",
+                      f"l2_read_latency_cycles: {mean('TCP_TCC_READ_REQ_LATENCY_sum', k) / max(req, 1):.1f}"]
     return "\n".join(lines) + "\n"
 
 
@@ -177,6 +216,7 @@ def main():
     ap.add_argument("--calib-bytes", type=int, default=0)
     ap.add_argument("--l2", help="rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum output")
     ap.add_argument("--sq", help="rocprofv3 --pmc SQ_INSTS_VALU ... OccupancyPercent output")
+    ap.add_argument("--mem", help="rocprofv3 --pmc " + " ".join(MEM_COUNTERS) + " output")
     ap.add_argument("--kernel", required=True)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--command", required=True)

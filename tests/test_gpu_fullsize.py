@@ -16,12 +16,15 @@ cone would poison the result instead of passing silently.  The subset keeps the
 box and its periodic axes, so minimum images are unchanged.
 
 Targets: 8 nearest each of 3 placed centres (open edges, periodic faces, the
-blob's core) and 64 uniformly random particles.  Neighbour sets are compared
-exactly.  Fields: within 1e-12 in FP64 (scaled as in the other parity tests);
+blob's core), 64 uniformly random particles, and 15 clusters of the 64 nearest
+particles to a random particle: 1,048 targets per workload.  Neighbour sets
+are compared exactly.  Fields: within 1e-12 in FP64 (scaled as in the other parity tests);
 in mixed precision h and the lists stay exact (FP64 Newton and FP64 test) and
 the fields are within 1e-5.
 
-The weakly compressible workloads take rho_ref = 1 (a generator-defined
+The step starts from the generator's state, not from the benchmark's set-up
+(whose h and reference densities come from the GPU, and no oracle input may),
+and the weakly compressible workloads take rho_ref = 1 (a generator-defined
 reference density) instead of the set-up's measured one.
 
 The C3 blob is also run for its 5 steps, from the benchmark's set-up, in FP64
@@ -44,6 +47,8 @@ TOL = 1e-12
 TOL_MIXED = 1e-5
 N_NEAR = 8      # targets per centre
 N_RANDOM = 64   # uniformly random targets
+N_CLUSTERS = 15  # clusters of the nearest particles to a random particle
+CLUSTER = 64     # targets per cluster
 
 FULL = {
     "c2": (inputs.c2_square_patch, [(0.0, 0.0, 0.0), (0.495, -0.495, 0.1), (0.2, -0.3, 0.4995)]),
@@ -239,6 +244,16 @@ def test_fullsize_sampled(name, precision):
     rng = np.random.default_rng(1000 + n % 997)
     for t in rng.choice(n, N_RANDOM, replace=False):
         groups.append((np.array([t]), np.array([a["x"][t], a["y"][t], a["z"][t]])))
+    for t in rng.choice(n, N_CLUSTERS, replace=False):
+        c = np.array([a["x"][t], a["y"][t], a["z"][t]])
+        rad = 2.0 * a["h"][t]
+        while True:
+            ids = grid.ball(c, rad)
+            if ids.size >= CLUSTER:
+                break
+            rad *= 1.5
+        near = ids[np.argsort(_r2(a, ids, c, w.params), kind="stable")[:CLUSTER]]
+        groups.append((near, c))
     worst = {}
     for tgt, c in groups:
         sub, lt, f = _oracle_cone(w, a, ocfg, kap, grid, tgt, c)
@@ -249,7 +264,8 @@ def test_fullsize_sampled(name, precision):
             {k: (TOL if k == "h" else TOL_MIXED) for k in errs}
         bad = {k: v for k, v in errs.items() if not v < bar[k]}
         assert not bad, (c, bad)
-    print(name, "mixed" if precision else "fp64", f"{len(groups)} groups",
+    print(name, "mixed" if precision else "fp64",
+          f"{sum(t.size for t, _ in groups)} targets in {len(groups)} groups",
           " ".join(f"{k}={v:.1e}" for k, v in worst.items()))
     G.free()
 
