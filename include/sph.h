@@ -9,7 +9,9 @@
  *   caller-owned, length cfg->n, stride 1, FP64 unless stated (structure of
  *   arrays).  The library allocates nothing and frees nothing; all scratch
  *   lives in the caller's workspace `ws`, except for sph_step_static, whose
- *   scratch is a fixed device array of the library (the only global state).
+ *   scratch is a fixed device array of the library (the only global state),
+ *   and the step graphs, whose HIP graph objects live from
+ *   sph_step_graph_create to sph_step_graph_destroy.
  * - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
  *   only enqueues work on it and returns; results are ready when the stream is.
  *   Two workspaces may be used concurrently on two streams.
@@ -215,6 +217,31 @@ sph_status sph_step(const sph_config* cfg, sph_particles* p, sph_globals* g, voi
 #define SPH_STEP_PHASES 8
 sph_status sph_step_marked(const sph_config* cfg, sph_particles* p, sph_globals* g, void* ws,
                            sph_stream stream, void* const* events, int32_t nevents);
+
+/* (host) A HIP graph of `steps` consecutive sph_step calls (section 4.1: the
+ * whole time step, `steps` times) on these particles, globals and workspace,
+ * replayed by one launch.  Small problems are bound by the launch cost of the
+ * step's ~40 kernels; a graph hands the device the whole sequence at once.
+ * The step is captured on a stream of the library's own (the caller's stream
+ * may be the legacy default stream, which cannot be captured) and nothing is
+ * run at creation; every sph_step_graph_launch then enqueues the steps on
+ * `stream` with exactly sph_step's kernels and arguments, so the results are
+ * bit-identical to `steps` calls of sph_step.  The graph keeps the pointers
+ * and the configuration it was created with: the arrays, globals and ws must
+ * stay allocated and be used by nothing else while a launch runs.  Device
+ * conditions accumulate in ws's error word as for sph_step (read them with
+ * sph_status_sync).
+ * Errors: SPH_E_ARG for an invalid config, NULL arguments or steps outside
+ * 1..SPH_GRAPH_MAX_STEPS; SPH_E_WORKSPACE for a NULL or misaligned ws;
+ * SPH_E_HIP if capture or instantiation fails (*graph is then NULL). */
+#define SPH_GRAPH_MAX_STEPS 1024
+typedef struct sph_step_graph_s* sph_step_graph;
+sph_status sph_step_graph_create(const sph_config* cfg, sph_particles* p, sph_globals* g,
+                                 void* ws, int32_t steps, sph_step_graph* graph);
+/* Enqueues the graph's steps on `stream`.  SPH_E_ARG for a NULL graph. */
+sph_status sph_step_graph_launch(sph_step_graph graph, sph_stream stream);
+/* Frees the graph (NULL is a no-op).  No launch of it may still be running. */
+void sph_step_graph_destroy(sph_step_graph graph);
 
 /* ------------------------------------------------------------------------
  * Self-gravity (section 4.1: a multipole expansion evaluated on the same

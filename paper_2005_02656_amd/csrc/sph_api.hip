@@ -7,6 +7,8 @@
 
 #include <mutex>
 
+#include <new>
+
 #include "sph_common.h"
 
 namespace sph {
@@ -446,6 +448,73 @@ sph_status sph_step_marked(const sph_config* cfg, sph_particles* p, sph_globals*
     hipError_t e = launch_integrate(c.P, c.W, p, g, c.s);
     mk.at(8, c.s);
     return hip_status(e);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- step graphs
+struct sph_step_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+sph_status sph_step_graph_create(const sph_config* cfg, sph_particles* p, sph_globals* g,
+                                 void* ws, int32_t steps, sph_step_graph* graph)
+{
+    if (!graph) return SPH_E_ARG;
+    *graph = nullptr;
+    if (steps < 1 || steps > SPH_GRAPH_MAX_STEPS) return SPH_E_ARG;
+    Ctx c;
+    sph_status st = prepare(cfg, ws, nullptr, c);
+    if (st) return st;
+    if (!step_args_ok(cfg, p, g)) return SPH_E_ARG;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SPH_E_HIP;
+    c.s = cs;
+    hipGraph_t gr = nullptr;
+    st = SPH_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = SPH_E_HIP;
+    } else {
+        for (int32_t k = 0; k < steps && st == SPH_OK; ++k) {
+            st = step_rates(c, p, g);
+            if (st == SPH_OK) st = hip_status(launch_integrate(c.P, c.W, p, g, c.s));
+        }
+        // the capture is always ended, whatever the steps returned
+        if (hipStreamEndCapture(cs, &gr) != hipSuccess && st == SPH_OK) st = SPH_E_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (st == SPH_OK && hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess)
+        st = SPH_E_HIP;
+    (void)hipStreamDestroy(cs);
+    sph_step_graph_s* h = nullptr;
+    if (st == SPH_OK) {
+        h = new (std::nothrow) sph_step_graph_s{gr, ex};
+        if (!h) st = SPH_E_HIP;
+    }
+    if (st != SPH_OK) {
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+    }
+    *graph = h;
+    return SPH_OK;
+}
+
+sph_status sph_step_graph_launch(sph_step_graph graph, sph_stream stream)
+{
+    if (!graph) return SPH_E_ARG;
+    return hip_status(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+}
+
+void sph_step_graph_destroy(sph_step_graph graph)
+{
+    if (!graph) return;
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 }  // extern "C"

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_HIP", 3: "SPH_E_WORKSPACE
 ERRBIT_NEIGHBOR_OVERFLOW, ERRBIT_CELL_RANGE, ERRBIT_NONFINITE, ERRBIT_SINGULAR_TAU = 1, 2, 4, 8
 SHORT_REACH = 1.03   # SPH_SHORT_REACH: the fused step's short candidate reach lambda
 STATIC_SCRATCH_BYTES = 64 << 20   # SPH_STATIC_SCRATCH_BYTES: sph_step_static's scratch
+GRAPH_MAX_STEPS = 1024   # SPH_GRAPH_MAX_STEPS: most steps one step graph captures
 KERNEL_TABLE_MAX = 65536          # SPH_KERNEL_TABLE_MAX
 KERNEL_TABLE_PAPER = 20000        # the table size of section 4.5
 FP64, MIXED = 0, 1
@@ -149,6 +150,10 @@ _SIGS = {
                                        C.c_void_p]),
     "sph_status_string": (C.c_char_p, [C.c_int]),
     "sph_step_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sph_step_graph_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_int32, C.c_void_p]),
+    "sph_step_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sph_step_graph_destroy": (None, [C.c_void_p]),
     "sph_gravity_workspace_bytes": (C.c_size_t, [C.c_void_p]),
     "sph_gravity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -306,6 +311,39 @@ def step(cfg: Config, parts: Particles, g: Globals, ws: Workspace, stream=None):
     ps = parts.c()
     _check(lib().sph_step(C.byref(cfg.c()), C.byref(ps), g.ptr, ws.ptr, _stream(stream)),
            "sph_step")
+
+
+class StepGraph:
+    """sph_step_graph_*: `steps` consecutive sph_step calls captured once as a
+    HIP graph and enqueued by launch() in one go (bit-identical to the calls).
+    Keeps the particles, globals and workspace alive: the graph holds their
+    device pointers."""
+
+    def __init__(self, cfg: Config, parts: Particles, g: Globals, ws: Workspace, steps: int = 1):
+        ps = parts.c()
+        h = C.c_void_p()
+        _check(lib().sph_step_graph_create(C.byref(cfg.c()), C.byref(ps), g.ptr, ws.ptr,
+                                           int(steps), C.byref(h)), "sph_step_graph_create")
+        self._h = h
+        self.steps = int(steps)
+        self._keep = (parts, g, ws)
+
+    def launch(self, stream=None):
+        if self._h is None:
+            raise RuntimeError("the step graph was closed")
+        _check(lib().sph_step_graph_launch(self._h, _stream(stream)), "sph_step_graph_launch")
+
+    def close(self):
+        if self._h is not None:
+            lib().sph_step_graph_destroy(self._h)
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 STEP_PHASES = ("build_cells", "candidates", "newton_h", "lists", "density", "iad",

@@ -40,6 +40,7 @@ def test_constants_match_the_header(sph):
     m = re.fullmatch(r"\((\d+)u << (\d+)\)", defs["SPH_STATIC_SCRATCH_BYTES"].strip())
     assert int(m.group(1)) << int(m.group(2)) == sph.STATIC_SCRATCH_BYTES
     assert int(defs["SPH_STEP_PHASES"]) == len(sph.STEP_PHASES)
+    assert int(defs["SPH_GRAPH_MAX_STEPS"]) == sph.GRAPH_MAX_STEPS
     shift = lambda d: 1 << int(re.fullmatch(r"\(1u << (\d+)\)", d.strip()).group(1))
     bits = {k: shift(defs["SPH_ERRBIT_" + k]) for k in
             ("NEIGHBOR_OVERFLOW", "CELL_RANGE", "NONFINITE", "SINGULAR_TAU")}
@@ -93,6 +94,34 @@ def test_static_step_rejects_before_enqueuing(sph):
     small = sph.Config(n=8000)
     assert L.sph_workspace_bytes(C.byref(small.c())) <= sph.STATIC_SCRATCH_BYTES
     assert L.sph_step_static(C.byref(small.c()), C.byref(parts), g, None, None) == 1
+
+
+def test_step_graph_rejects_before_capturing(sph):
+    """sph_step_graph_create validates on the host and leaves *graph NULL:
+    SPH_E_ARG for a NULL handle, steps outside 1..SPH_GRAPH_MAX_STEPS, a bad
+    config or NULL particles, SPH_E_WORKSPACE for a misaligned workspace; a
+    NULL graph is refused by launch and ignored by destroy."""
+    L = sph.lib()
+    cfg = sph.Config(n=1000)
+    parts = sph._Particles()
+    g = C.c_void_p(256)
+    ws = C.c_void_p(256)
+    h = C.c_void_p(1234)
+    assert L.sph_step_graph_create(C.byref(cfg.c()), C.byref(parts), g, ws, 1, None) == 1
+    for steps in (0, -1, sph.GRAPH_MAX_STEPS + 1):
+        assert L.sph_step_graph_create(C.byref(cfg.c()), C.byref(parts), g, ws, steps,
+                                       C.byref(h)) == 1
+        assert h.value is None
+        h = C.c_void_p(1234)
+    assert L.sph_step_graph_create(C.byref(cfg.replace(n=0).c()), C.byref(parts), g, ws, 1,
+                                   C.byref(h)) == 1
+    assert L.sph_step_graph_create(C.byref(cfg.c()), C.byref(parts), g, C.c_void_p(17), 1,
+                                   C.byref(h)) == 3
+    assert L.sph_step_graph_create(C.byref(cfg.c()), None, g, ws, 1, C.byref(h)) == 1
+    assert L.sph_step_graph_create(C.byref(cfg.c()), C.byref(parts), g, ws, 1,
+                                   C.byref(h)) == 1   # the particle arrays are NULL
+    assert L.sph_step_graph_launch(None, None) == 1
+    L.sph_step_graph_destroy(None)
 
 
 def test_status_strings(sph):
