@@ -1,8 +1,9 @@
 """Benchmark of the SPH time step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
-                    [--precision fp64|mixed] [--no-cpu-baseline] [--no-mixed]
-                    [--no-adjoint] [--no-table] [--no-gravity] [--oracle-points]
+                    [--precision fp64|mixed] [--no-cpu-baseline] [--no-graph]
+                    [--no-mixed] [--no-adjoint] [--no-table] [--no-gravity]
+                    [--oracle-points]
 
 A step is one sph_step (Morton sort into cells, Newton h update, neighbour
 search, density, IAD, momentum/energy with AV, global dt, integration and
@@ -11,7 +12,8 @@ The set-up (initial conditions, upload, the Newton initialisation of h and the
 reference density) is untimed.  The timed steps run through sph_step_marked
 (the same launches plus HIP events between phases) so the per-phase times and
 the roofline of the longest phase come from the timed steps themselves.  Then,
-unless switched off: the same workload in mixed precision, the kernel
+unless switched off: the same steps replayed from a one-step HIP graph, the
+same workload in mixed precision, the kernel
 lookup-table variant (FP64 and mixed), the adjoint/forward
 time of the 64^3 rollout, the self-gravity tree walk on an 8 M-particle sphere,
 and the FP64 oracle timed on the host on a bounded sample.  Prints ONE JSON line.
@@ -88,6 +90,8 @@ def parse():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the timing of the step replayed from a HIP graph")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision timing of the same workload")
     ap.add_argument("--no-gravity", action="store_true",
@@ -374,6 +378,26 @@ def main():
                       + FLOPS_PER_PAIR["lists"] * k_g + FLOPS_PER_PAIR["iad"] * k_g
                       + FLOPS_PER_PAIR["momentum_energy"] * k_s)
     out["step_fp64_valu_frac"] = step_flops / (ms * 1e-3) / (FP64_VALU_PEAK_TFLOPS * 1e12)
+
+    if not args.no_graph:
+        # the same step replayed from a one-step HIP graph (sph_step_graph):
+        # what the eager steps lose to launching ~40 kernels one by one
+        sg = sph.StepGraph(cfg, parts, g, ws, steps=1)
+        sg.launch(stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(args.steps):
+            sg.launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / args.steps
+        sg.close()
+        st, bits = sph.status_sync(ws)
+        if st:
+            raise RuntimeError(f"graph steps raised {sph.status_string(st)} (bits {bits})")
+        out["graph"] = {"ms_per_step": gms, "value": n / (gms * 1e-3),
+                        "note": "the same step replayed from a one-step HIP graph"}
+        log(f"[bench] graph replay: {gms:.3f} ms/step")
 
     if not args.no_mixed and prec == sph.FP64:
         mcfg = cfg.replace(precision=sph.MIXED)
