@@ -146,8 +146,6 @@ def roofline(phases, n, k_g, k_s, wc, iters, k_c, workload, fused, urec=False):
     by = bytes_per_particle(dom, k_g, k_s, wc, k_c, iters, fused, urec)
     hbm = by * n / t / 1e9
     kern = PHASE_KERNEL[dom]
-    if dom == "momentum_energy" and urec:
-        kern = "k_momentum_energy_u"   # the kernel of the 112-byte records
     traffic = traffic_from_profile(kern, workload)
     res = {"kernel": kern, "phase": dom, "phase_ms": phases[dom], "traffic": traffic,
            "algorithmic_bytes": by * n,

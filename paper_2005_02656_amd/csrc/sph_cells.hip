@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const double* __restrict__ x,
     }
     __shared__ double s[kWaves][7];
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (__ballot(mv) && lane == 0) atomicOr(&d->mass_varies, 1u);
+    if (__ballot(mv) && lane == 0) flag_or(&d->mass_varies, 1u);
     double r[7];
     for (int k = 0; k < 3; ++k) r[k] = wave_min(mn[k]);
     for (int k = 0; k < 4; ++k) r[3 + k] = wave_max(mx[k]);

@@ -240,7 +240,16 @@ SPH_HD double ord_value(uint64_t o)
     return __builtin_bit_cast(double, b);
 }
 
-SPH_DEV void set_err(Domain* d, uint32_t bit) { atomicOr(&d->err, bit); }
+// Sets bits of a flag word that only gains bits: a wavefront that reads them
+// already set skips the atomic (one atomic per wavefront on one address
+// serialises: 125 K of them made the 8 M-particle uniformity check take 1 ms).
+SPH_DEV void flag_or(uint32_t* p, uint32_t bits)
+{
+    if ((__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bits) != bits)
+        atomicOr(p, bits);
+}
+
+SPH_DEV void set_err(Domain* d, uint32_t bit) { flag_or(&d->err, bit); }
 
 // Global minimum / maximum of order-preserving bits.  The held value only moves
 // one way, so a wavefront whose value is no better than one it reads cannot
@@ -552,9 +561,6 @@ inline void with_table(const Params& P, F&& f)
 #endif
 #ifndef SPH_MOM_ATTR
 #define SPH_MOM_ATTR SPH_WAVES_CAP(SPH_WAVES_MOM)
-#endif
-#ifndef SPH_MOM_U_ATTR
-#define SPH_MOM_U_ATTR SPH_WAVES_EXACT(2)
 #endif
 #ifndef SPH_WAVES_CAND
 #define SPH_WAVES_CAND 7

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_uniform_check(int64_t n, const doubl
 {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     const bool diff = i < n && (m[i] != m[0] || c[i] != c[0]);
-    if (__ballot(diff) && (threadIdx.x & 63) == 0) atomicOr(&dom->nonuniform, 1u);
+    if (__ballot(diff) && (threadIdx.x & 63) == 0) flag_or(&dom->nonuniform, 1u);
 }
 
 template <int kPer, bool kTab>
@@ -457,46 +457,34 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
         ord_min_to(&dom->dtmin_bits, dtc);
 }
 
-// One kernel per record layout; both are launched and the one the uniformity
-// flag did not select returns at once.  The 144-byte records gather per lane in
-// batches of 4 at two wavefronts per SIMD (they spill at three); the 112-byte
-// records are staged through LDS in batches of 2 at two wavefronts (at 64 M
-// particles 48.9 ms; per-lane gathers took 52.4 ms at three wavefronts and
-// batches of 3, 54.9 at two and batches of 4).
+// One kernel for both record layouts, the uniformity flag choosing the path:
+// the 144-byte records gather per lane in batches of 4, the 112-byte records
+// are staged through LDS in batches of 2, both at two wavefronts per SIMD (the
+// 144-byte path spills at three; the staging's LDS allows two).  At 64 M
+// particles the staged path takes 47.5 ms; per-lane gathers took 52.4 ms at
+// three wavefronts and batches of 3, 54.9 at two and batches of 4.  (Two
+// kernels, one returning at once, cost the unselected launch 2.6 ms at 8 M
+// particles: its LDS held the workgroups of the empty launch to two per CU.)
 template <int kPer, bool kTab>
 __global__ __launch_bounds__(kBlock) SPH_MOM_ATTR void k_momentum_energy(Params P, Domain* __restrict__ dom,
                                                             const int32_t* __restrict__ nc,
                                                             const int32_t* __restrict__ ns,
                                                             const int32_t* __restrict__ list,
-                                                            const MomNbr* __restrict__ rec,
+                                                            const void* __restrict__ rec,
                                                             MomSelf T,
                                                             const double* __restrict__ u,
                                                             MomOut O)
 {
-    if (dom->nonuniform == 0u) return;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
-    momentum_energy<MomNbr, SPH_MOM_BATCH, kPer, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
-}
-
-template <int kPer, bool kTab>
-__global__ __launch_bounds__(kBlock) SPH_MOM_U_ATTR void k_momentum_energy_u(Params P, Domain* __restrict__ dom,
-                                                                const int32_t* __restrict__ nc,
-                                                                const int32_t* __restrict__ ns,
-                                                                const int32_t* __restrict__ list,
-                                                                const MomNbrU* __restrict__ rec,
-                                                                MomSelf T,
-                                                                const double* __restrict__ u,
-                                                                MomOut O)
-{
-    if (dom->nonuniform != 0u) return;
-    const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    const int64_t lb = xcd_block(nb);
-    if (lb < 0) return;
-    const int64_t a = lb * kBlock + threadIdx.x;
-    momentum_energy<MomNbrU, SPH_MOM_U_BATCH, kPer, kTab>(P, dom, nc, ns, list, rec, T, u, O, a);
+    if (dom->nonuniform != 0u)
+        momentum_energy<MomNbr, SPH_MOM_BATCH, kPer, kTab>(P, dom, nc, ns, list,
+                                                           (const MomNbr*)rec, T, u, O, a);
+    else
+        momentum_energy<MomNbrU, SPH_MOM_U_BATCH, kPer, kTab>(P, dom, nc, ns, list,
+                                                              (const MomNbrU*)rec, T, u, O, a);
 }
 
 __global__ void k_timestep(Params P, const Domain* __restrict__ dom, sph_globals* g)
@@ -587,10 +575,8 @@ hipError_t launch_momentum_energy(const Params& P, const Layout& L, const Ws& W,
         with_table(P, [&](auto tab) {
             constexpr int kPer = decltype(per)::value;
             constexpr bool kTab = decltype(tab)::value;
-            k_momentum_energy_u<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
-                P, W.dom, W.nc, W.ns, W.list, (const MomNbrU*)W.rec, T, p->u, O);
             k_momentum_energy<kPer, kTab><<<grid_xcd(nb), kBlock, 0, s>>>(
-                P, W.dom, W.nc, W.ns, W.list, (const MomNbr*)W.rec, T, p->u, O);
+                P, W.dom, W.nc, W.ns, W.list, (const void*)W.rec, T, p->u, O);
         });
     });
     return hipGetLastError();

@@ -562,7 +562,7 @@ __device__ __forceinline__ void update_h_list(const Params& P, Domain* __restric
     // (2) and clears the others (0); the full-reach pass recomputes the former
     if (!full) flag[a] = over ? 2 : 0;
     if (over) {
-        atomicOr(&dom->refit, 1u);
+        flag_or(&dom->refit, 1u);
     } else {
         check_cell_range(P, dom, hc);
     }

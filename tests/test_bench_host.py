@@ -67,16 +67,18 @@ def test_roofline_reports_the_binding_ceiling():
     r4 = bench.roofline({**phases, "candidates": 100.0}, n, k_g, k_s, True, 2, k_c,
                         "no-such-workload", True)
     assert r4["phase"] == "momentum_energy"
-    # with equal masses and sound speeds the momentum phase runs its own kernel
+    # with equal masses and sound speeds the same kernel reads 112-byte records
     r3 = bench.roofline(phases, n, k_g, k_s, True, 2, k_c, "c4", True, urec=True)
-    assert r3["kernel"] == "k_momentum_energy_u"
+    assert r3["kernel"] == "k_momentum_energy"
+    assert r3["algorithmic_bytes"] == pytest.approx(
+        bench.bytes_per_particle("momentum_energy", k_g, k_s, True, k_c, 2, True, True) * n)
 
 
 def test_traffic_comes_from_a_summary_of_the_current_sources(tmp_path):
     # C4 has equal masses under the weakly compressible EOS: 112-byte records
-    s = profiling.read_summary(os.path.join(ROOT, "profiles", "k_momentum_energy_u_c4.md"))
+    s = profiling.read_summary(os.path.join(ROOT, "profiles", "k_momentum_energy_c4.md"))
     assert s, "no committed summary for the C4 momentum kernel"
-    t = bench.traffic_from_profile("k_momentum_energy_u", "c4")
+    t = bench.traffic_from_profile("k_momentum_energy", "c4")
     if s.get("source_digest") == profiling.source_digest():
         assert t == pytest.approx(float(s["fetch_bytes_per_launch"])
                                   + float(s["write_bytes_per_launch"]))
