@@ -18,7 +18,7 @@
 namespace sph {
 namespace {
 
-constexpr int kGravBlock = 128;
+constexpr int kGravBlock = 256;
 constexpr int kGravStack = 7 * kMaxLevel + 1;   // deepest depth-first stack
 
 struct alignas(16) GNode {
@@ -160,8 +160,15 @@ struct GravOut {
     double *gx, *gy, *gz;
 };
 
-// the walk of one target per lane; the depth-first stack (level << 27 | index)
-// lives in LDS, one column per lane
+// The walk.  Each lane takes one target, and the 64 lanes of a wavefront walk
+// the tree together: a node is loaded once for the wavefront (its address is
+// uniform), every lane still live at it applies its own opening test, the
+// lanes that accept it add its expansion, and the node is opened for the lanes
+// that do not (children pushed with that lane set).  A lane's terms are thus
+// the nodes and particles its own depth-first walk would visit, in the same
+// order: the result is that of one walk per target, bit for bit, while the
+// traversal and its loads are shared.  The stack (level << 27 | index, and the
+// 64-bit set of lanes still live below the entry) is uniform and lives in LDS.
 __global__ __launch_bounds__(kGravBlock) void k_gravity(GLevels T, const Domain* __restrict__ dom,
                                                         const uint64_t* __restrict__ keys,
                                                         const double* __restrict__ x,
@@ -171,10 +178,13 @@ __global__ __launch_bounds__(kGravBlock) void k_gravity(GLevels T, const Domain*
                                                         double G, double eps, double theta,
                                                         GravOut O)
 {
-    __shared__ uint32_t stack[kGravStack][kGravBlock];
-    const int t = threadIdx.x;
-    const int64_t a = blockIdx.x * (int64_t)kGravBlock + t;
-    if (a >= n) return;
+    constexpr int kWaves = kGravBlock / 64;
+    __shared__ uint32_t st_node[kWaves][kGravStack];
+    __shared__ uint64_t st_live[kWaves][kGravStack];
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    const int64_t a0 = blockIdx.x * (int64_t)kGravBlock + threadIdx.x;
+    const bool live0 = a0 < n;
+    const int64_t a = live0 ? a0 : n - 1;   // lanes past the end shadow the last target
     const double xa = x[a], ya = y[a], za = z[a];
     const uint64_t ka = keys[a];
     double ext = 0.0;
@@ -182,15 +192,31 @@ __global__ __launch_bounds__(kGravBlock) void k_gravity(GLevels T, const Domain*
     const double eps2 = eps * eps, th2 = theta * theta;
     double gx = 0.0, gy = 0.0, gz = 0.0;
     int sp = 0;
-    stack[sp++][t] = 0u;   // the root
+    const uint64_t all = __ballot(live0);
+    if (lane == 0) {
+        st_node[wv][0] = 0u;   // the root
+        st_live[wv][0] = all;
+    }
+    sp = 1;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     while (sp > 0) {
-        const uint32_t top = stack[--sp][t];
+        --sp;
+        // (the builtin reads and returns int: each half goes back through
+        // uint32_t, so that the low half is not sign-extended)
+        const uint32_t top = (uint32_t)__builtin_amdgcn_readfirstlane((int)st_node[wv][sp]);
+        const uint64_t lv = st_live[wv][sp];
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(lv >> 32));
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)lv);
+        const uint64_t lmask = ((uint64_t)hi << 32) | (uint64_t)lo;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int l = (int)(top >> 27);
         const uint32_t idx = top & ((1u << 27) - 1u);
         const GNode nd = T.lev[l][idx];
         if (nd.e <= nd.s) continue;
+        const bool mine = (lmask >> lane) & 1u;
         const bool own = (ka >> (3 * (kKeyBits - l))) == (uint64_t)idx;
-        if (!own) {
+        bool open = mine;
+        if (mine && !own) {
             const double dx = xa - nd.cx, dy = ya - nd.cy, dz = za - nd.cz;
             const double d2 = dx * dx + dy * dy + dz * dz;
             const double sz = ext / (double)(1 << l);
@@ -207,15 +233,19 @@ __global__ __launch_bounds__(kGravBlock) void k_gravity(GLevels T, const Domain*
                 gx += -G * nd.M * dx * ir3 + G * (Qx * ir5 - 2.5 * rQr * dx * ir7);
                 gy += -G * nd.M * dy * ir3 + G * (Qy * ir5 - 2.5 * rQr * dy * ir7);
                 gz += -G * nd.M * dz * ir3 + G * (Qz * ir5 - 2.5 * rQr * dz * ir7);
-                continue;
+                open = false;
             }
         }
+        const uint64_t omask = __ballot(open);
+        if (omask == 0) continue;
         if (l == T.L) {
+            // an opened leaf: its particles directly, in slot order
             for (int32_t b = nd.s; b < nd.e; ++b) {
-                if (b == (int32_t)a) continue;
-                const double dx = xa - x[b], dy = ya - y[b], dz = za - z[b];
+                const double xb = x[b], yb = y[b], zb = z[b], mb = m[b];
+                if (!open || b == (int32_t)a) continue;
+                const double dx = xa - xb, dy = ya - yb, dz = za - zb;
                 const double r2 = dx * dx + dy * dy + dz * dz + eps2;
-                const double f = G * m[b] / (r2 * sqrt(r2));
+                const double f = G * mb / (r2 * sqrt(r2));
                 gx -= f * dx;
                 gy -= f * dy;
                 gz -= f * dz;
@@ -224,8 +254,16 @@ __global__ __launch_bounds__(kGravBlock) void k_gravity(GLevels T, const Domain*
         }
         // children, last first, so that the walk visits them in ascending prefix
         const uint32_t base = (uint32_t)(l + 1) << 27;
-        for (int k = 7; k >= 0; --k) stack[sp++][t] = base | (idx * 8u + (uint32_t)k);
+        if (lane == 0) {
+            for (int k = 7; k >= 0; --k) {
+                st_node[wv][sp + 7 - k] = base | (idx * 8u + (uint32_t)k);
+                st_live[wv][sp + 7 - k] = omask;
+            }
+        }
+        sp += 8;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
+    if (!live0) return;
     O.gx[a] = gx;
     O.gy[a] = gy;
     O.gz[a] = gz;
