@@ -239,17 +239,31 @@ __global__ __launch_bounds__(kGravBlock) void k_gravity(GLevels T, const Domain*
         const uint64_t omask = __ballot(open);
         if (omask == 0) continue;
         if (l == T.L) {
-            // an opened leaf: its particles directly, in slot order
-            for (int32_t b = nd.s; b < nd.e; ++b) {
-                const double xb = x[b], yb = y[b], zb = z[b], mb = m[b];
-                if (!open || b == (int32_t)a) continue;
+            // an opened leaf: its particles directly, in slot order (four
+            // particles' loads issued together)
+            auto direct = [&](int32_t b, double xb, double yb, double zb, double mb) {
+                if (!open || b == (int32_t)a) return;
                 const double dx = xa - xb, dy = ya - yb, dz = za - zb;
                 const double r2 = dx * dx + dy * dy + dz * dz + eps2;
                 const double f = G * mb / (r2 * sqrt(r2));
                 gx -= f * dx;
                 gy -= f * dy;
                 gz -= f * dz;
+            };
+            int32_t b = nd.s;
+            for (; b + 4 <= nd.e; b += 4) {
+                double xb[4], yb[4], zb[4], mb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xb[u] = x[b + u];
+                    yb[u] = y[b + u];
+                    zb[u] = z[b + u];
+                    mb[u] = m[b + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) direct(b + u, xb[u], yb[u], zb[u], mb[u]);
             }
+            for (; b < nd.e; ++b) direct(b, x[b], y[b], z[b], m[b]);
             continue;
         }
         // children, last first, so that the walk visits them in ascending prefix
