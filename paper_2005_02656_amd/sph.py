@@ -11,6 +11,7 @@ import ctypes as C
 import dataclasses
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -215,35 +216,43 @@ class Workspace:
 
 
 class Particles:
-    """Device arrays of one particle set (torch tensors, FP64 SoA; id int64)."""
+    """Device arrays of one particle set (torch tensors, FP64 SoA; id int64).
+    The FP64 fields of a step's state (SNAP_FIELDS) are the rows of one block,
+    so that a checkpoint is one copy."""
 
-    def __init__(self, tensors: dict):
+    def __init__(self, tensors: dict, block: torch.Tensor = None):
         self.t = tensors
+        self.block = block   # (fields, n) FP64 storage of the state rows, or None
 
     @classmethod
     def from_arrays(cls, arrays: dict, cfg: Config, device="cuda") -> "Particles":
         n = cfg.n
-        t = {}
+        src = {}
         for k in ("x", "y", "z", "vx", "vy", "vz", "h", "m", "u"):
-            t[k] = torch.as_tensor(arrays[k], dtype=torch.float64).to(device).contiguous()
-        for k, src in (("vhx", "vx"), ("vhy", "vy"), ("vhz", "vz")):
-            t[k] = torch.as_tensor(arrays.get(k, arrays[src]), dtype=torch.float64).to(device).clone()
-        if "du_m1" in arrays:
-            t["du_m1"] = torch.as_tensor(arrays["du_m1"], dtype=torch.float64).to(device).clone()
-        else:
-            t["du_m1"] = torch.zeros(n, dtype=torch.float64, device=device)
-        t["id"] = torch.as_tensor(arrays["id"], dtype=torch.int64).to(device).contiguous()
+            src[k] = arrays[k]
+        for k, s0 in (("vhx", "vx"), ("vhy", "vy"), ("vhz", "vz")):
+            src[k] = arrays.get(k, arrays[s0])
+        src["du_m1"] = arrays.get("du_m1", np.zeros(n))
         if cfg.eos == 1:
-            t["p_ref"] = torch.as_tensor(arrays["p_ref"], dtype=torch.float64).to(device).contiguous()
-            t["rho_ref"] = (torch.as_tensor(arrays["rho_ref"], dtype=torch.float64).to(device)
-                            .contiguous() if "rho_ref" in arrays
-                            else torch.zeros(n, dtype=torch.float64, device=device))
+            src["p_ref"] = arrays["p_ref"]
+            src["rho_ref"] = arrays.get("rho_ref", np.zeros(n))
+        for k, v in src.items():
+            if np.size(v) != n:
+                raise ValueError(f"field {k} has {np.size(v)} entries, expected {n}")
+        rows = [k for k in SNAP_FIELDS if k in src]
+        # rows padded to 256 bytes, so that every field starts aligned
+        npad = (n + 31) // 32 * 32
+        block = torch.zeros((len(rows), npad), dtype=torch.float64, device=device)
+        t = {}
+        for i, k in enumerate(rows):
+            t[k] = block[i, :n]
+            t[k].copy_(torch.as_tensor(src[k], dtype=torch.float64))
+        t["id"] = torch.as_tensor(arrays["id"], dtype=torch.int64).to(device).contiguous()
         for k in OUT_FIELDS:
             t[k] = torch.zeros(n, dtype=torch.float64, device=device)
-        for k, v in t.items():
-            if v.numel() != n:
-                raise ValueError(f"field {k} has {v.numel()} entries, expected {n}")
-        return cls(t)
+        if t["id"].numel() != n:
+            raise ValueError(f"field id has {t['id'].numel()} entries, expected {n}")
+        return cls(t, block)
 
     def __getitem__(self, k):
         return self.t[k]
@@ -548,18 +557,33 @@ SNAP_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "h", "m", "
 
 
 def snapshot(parts: Particles, g: Globals) -> dict:
-    """Device copy of the state arrays and the globals (a step checkpoint)."""
-    snap = {k: parts.t[k].clone() for k in SNAP_FIELDS if k in parts.t}
-    snap["_globals"] = g.t.clone()
+    """Device copy of the state arrays and the globals (a step checkpoint):
+    one copy of the state block (its rows are also given by name), the ids and
+    the globals."""
+    snap = {"_globals": g.t.clone(), "id": parts.t["id"].clone()}
+    if parts.block is not None:
+        b = parts.block.clone()
+        snap["_block"] = b
+        n = parts.t["id"].numel()
+        rows = [k for k in SNAP_FIELDS if k in parts.t and k != "id"]
+        for i, k in enumerate(rows):
+            snap[k] = b[i, :n]
+    else:
+        for k in SNAP_FIELDS:
+            if k in parts.t and k != "id":
+                snap[k] = parts.t[k].clone()
     return snap
 
 
 def restore(parts: Particles, g: Globals, snap: dict):
-    for k, v in snap.items():
-        if k == "_globals":
-            g.t.copy_(v)
-        else:
-            parts.t[k].copy_(v)
+    g.t.copy_(snap["_globals"])
+    parts.t["id"].copy_(snap["id"])
+    if "_block" in snap and parts.block is not None:
+        parts.block.copy_(snap["_block"])
+    else:
+        for k in SNAP_FIELDS:
+            if k in snap and k != "id":
+                parts.t[k].copy_(snap[k])
 
 
 def density_eval(cfg: Config, parts: Particles, ws: Workspace, stream=None):
