@@ -63,6 +63,11 @@ Layout make_layout(int64_t n, int ng_max)
     L.tabSf = take(sizeof(float2) * SPH_KERNEL_TABLE_MAX);
     L.tabDf = take(sizeof(float2) * SPH_KERNEL_TABLE_MAX);
     L.flag = take(sizeof(uint8_t) * n);
+    // the walk's reach bounds: the block maxima of every level below the
+    // finest (1 + 8 + ... + 8^(lcap-1)), then the bound of each block
+    size_t levels = 0;
+    for (int l = 0; l < lcap; ++l) levels += size_t(1) << (3 * l);
+    L.reach = take(sizeof(double) * (levels + (size_t)L.ncells_cap));
     L.total = o;
     return L;
 }
@@ -100,6 +105,7 @@ Ws carve(void* ws, const Layout& L)
     W.tabSf = (float2*)(b + L.tabSf);
     W.tabDf = (float2*)(b + L.tabDf);
     W.flag = (uint8_t*)(b + L.flag);
+    W.reach = (double*)(b + L.reach);
     return W;
 }
 

@@ -75,6 +75,7 @@ struct Domain {
     uint32_t refit;            // fused step: an h left the short candidate reach
     uint32_t nonuniform;       // some m or c differs from slot 0's (full momentum records)
     uint32_t mass_varies;      // some m differs from slot 0's (set by the cell build)
+    int32_t reach_level;       // fused step: level of the blocks that bound each walk's reach
     float walk_slack;          // 2^-20 x the largest extent (FP32 candidate walk)
     int64_t built_n;
 };
@@ -191,7 +192,7 @@ struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
     size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm, mf, mf2;
     size_t tabS, tabD, tabSf, tabDf;
-    size_t flag;
+    size_t flag, reach;
     size_t total;
     int64_t n, nsort_blocks, hist_len, scan_blocks, ncells_cap;
     int lcap, cand_cap;
@@ -221,6 +222,7 @@ struct Ws {
     double2 *tabS, *tabD;      // kernel tables (kernel_table > 0), FP64 and FP32
     float2 *tabSf, *tabDf;
     uint8_t* flag;             // fused step: 2 h left the short reach, 1 a neighbour of one
+    double* reach;             // fused step: per-block h bounds of the walk (levels, then reach)
 };
 Ws carve(void* ws, const Layout& L);
 

@@ -269,6 +269,113 @@ __global__ __launch_bounds__(kBlock) void k_cells_hmax(Params P, Domain* __restr
     }
 }
 
+// ---------------------------------------------------------------- walk reach
+// The fused walk's stencil must hold every b within 2 kap max(h_a, h_b) of its
+// target.  With one global bound (the largest h) the free surfaces and the
+// thin outskirts of a cluster size every target's stencil.  Instead: blocks of
+// the Morton octree at a level lc whose edge E exceeds 2 kappa h_max (plus the
+// rounding of the keys and of the walk's FP32 test) bound h_b by the largest h
+// of the target's block and its 26 neighbours (periodic axes wrap).  A b
+// outside those blocks is at least one block edge away, E > 2 kap max(h_a, h_b),
+// so it can be no candidate; a b inside has h_b at most that bound.  Each walk
+// then reaches 2 kap max(h_a, H(block of a)).
+
+// offset of level l in the table of block maxima (levels 0 .. finest-1)
+__host__ __device__ inline int64_t reach_level_offset(int l)
+{
+    int64_t o = 0;
+    for (int k = 0; k < l; ++k) o += int64_t(1) << (3 * k);
+    return o;
+}
+
+// the block level: the finest level below the cells whose block edge on every
+// axis with extent exceeds the bound (level 0, one block, when none does)
+__global__ void k_reach_level(Params P, Domain* d)
+{
+    const double need = 2.0 * P.kappa * ord_value(d->hmax_new_bits);
+    double emin = INFINITY, emax = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double e = d->hi[k] - d->lo[k];
+        if (e > 0.0) {
+            emin = fmin(emin, e);
+            emax = fmax(emax, e);
+        }
+    }
+    // four key units and the walk's slack (2^-20 of the extent) cover the
+    // quantised block boundaries and the FP32 test's widened reach
+    const double margin = 4.0 * emax * 0x1p-21 + 2.0 * emax * 0x1p-20;
+    int lc = 0;
+    for (int l = d->level - 1; l > 0; --l) {
+        if ((emin / (double)(1 << l)) * (1.0 - 1e-9) >= need * (1.0 + 0x1p-18) + margin) {
+            lc = l;
+            break;
+        }
+    }
+    d->reach_level = lc;
+}
+
+// block maxima of level l from level l + 1 (the cells when l + 1 is the finest)
+__global__ __launch_bounds__(kBlock) void k_reach_up(const Domain* __restrict__ d,
+                                                     const CellRange* __restrict__ cells,
+                                                     double* __restrict__ tab, int l)
+{
+    const int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (l >= d->level || l < d->reach_level || c >= (int64_t(1) << (3 * l))) return;
+    double m = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t ch = 8 * c + k;
+        m = fmax(m, (l + 1 == d->level) ? cells[ch].hmax : tab[reach_level_offset(l + 1) + ch]);
+    }
+    tab[reach_level_offset(l) + c] = m;
+}
+
+__device__ __forceinline__ uint32_t compact10(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
+
+// the bound of each block at the block level: the largest h of it and its 26
+// neighbours (wrapped on periodic axes, clipped on open ones)
+__global__ __launch_bounds__(kBlock) void k_reach_bound(Params P, const Domain* __restrict__ d,
+                                                        const CellRange* __restrict__ cells,
+                                                        const double* __restrict__ tab,
+                                                        double* __restrict__ bound)
+{
+    const int lc = d->reach_level;
+    const int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (c >= (int64_t(1) << (3 * lc))) return;
+    const int nb = 1 << lc;
+    const int b[3] = {(int)compact10((uint32_t)c >> 2), (int)compact10((uint32_t)c >> 1),
+                      (int)compact10((uint32_t)c)};
+    const double* lev = tab + reach_level_offset(lc);
+    double m = 0.0;
+    for (int ox = -1; ox <= 1; ++ox) {
+        for (int oy = -1; oy <= 1; ++oy) {
+            for (int oz = -1; oz <= 1; ++oz) {
+                int q[3] = {b[0] + ox, b[1] + oy, b[2] + oz};
+                bool in = true;
+                for (int k = 0; k < 3; ++k) {
+                    if (q[k] < 0 || q[k] >= nb) {
+                        if (P.periodic[k]) q[k] = (q[k] + nb) % nb;
+                        else in = false;
+                    }
+                }
+                if (!in) continue;
+                const uint32_t cc = (spread10((uint32_t)q[0]) << 2) |
+                                    (spread10((uint32_t)q[1]) << 1) | spread10((uint32_t)q[2]);
+                // (a single cell, level 0, is its own block)
+                m = fmax(m, lc == d->level ? cells[cc].hmax : lev[cc]);
+            }
+        }
+    }
+    bound[c] = m;
+}
+
 // symmetric neighbour lists: gather members of N(a) from the front of the
 // tile row, members of N_s(a) \ N(a) from the back
 __global__ __launch_bounds__(kBlock) void k_find_neighbors(Params P, Domain* __restrict__ dom,
@@ -343,7 +450,9 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
                                            const Pos4* __restrict__ p4,
                                            const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
                                            int32_t* __restrict__ cand, double kap, float sc,
-                                           uint8_t* __restrict__ flag)
+                                           uint8_t* __restrict__ flag,
+                                           const uint64_t* __restrict__ keys,
+                                           const double* __restrict__ reach)
 {
     constexpr bool kFull = kMode != 0;
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
@@ -357,7 +466,8 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
     const Pos4 pa = p4[a];
     const Pos4f fa = pf[a];
     const uint32_t far2 = __float_as_uint(kFull ? fa.r2 * sc : fa.r2);
-    const double hmax0 = ord_value(D.hmax_new_bits);
+    // the largest h the target's candidates can have (its block's bound)
+    const double hreach = reach[keys[a] >> (3 * (kKeyBits - D.reach_level))];
     const int cap = P.cand_cap;
     // candidates are staged in LDS, column per lane, and written out in
     // whole chunks of 8 (two 16-byte stores per lane)
@@ -366,7 +476,7 @@ __device__ __forceinline__ void candidates(const Params& P, Domain* __restrict__
     const int32_t self = (int32_t)a;
     int k = 0;
     walk_cells(
-        P, D, cells, pf, pa.x, pa.y, pa.z, 2.0 * kap * fmax(pa.h, hmax0),
+        P, D, cells, pf, pa.x, pa.y, pa.z, 2.0 * kap * fmax(pa.h, hreach),
         [&](const CellRange& cr, double g2) {
             double hc = 2.0 * kap * fmax(pa.h, cr.hmax);
             return g2 < hc * hc;
@@ -416,18 +526,20 @@ template <int kPer>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-    int32_t* __restrict__ cand, double kap, float sc, uint8_t* __restrict__ flag)
+    int32_t* __restrict__ cand, double kap, float sc, uint8_t* __restrict__ flag,
+    const uint64_t* __restrict__ keys, const double* __restrict__ reach)
 {
-    candidates<kPer, 0>(P, dom, cells, p4, pf, nk, cand, kap, sc, flag);
+    candidates<kPer, 0>(P, dom, cells, p4, pf, nk, cand, kap, sc, flag, keys, reach);
 }
 template <int kPer, int kMode>
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates_full(
     Params P, Domain* __restrict__ dom, const CellRange* __restrict__ cells,
     const Pos4* __restrict__ p4, const Pos4f* __restrict__ pf, int32_t* __restrict__ nk,
-    int32_t* __restrict__ cand, double kap, float sc, uint8_t* __restrict__ flag)
+    int32_t* __restrict__ cand, double kap, float sc, uint8_t* __restrict__ flag,
+    const uint64_t* __restrict__ keys, const double* __restrict__ reach)
 {
     if (dom->refit == 0u) return;
-    candidates<kPer, kMode>(P, dom, cells, p4, pf, nk, cand, kap, sc, flag);
+    candidates<kPer, kMode>(P, dom, cells, p4, pf, nk, cand, kap, sc, flag, keys, reach);
 }
 
 // the candidate pass for the periodic axes of P: mode 0 short reach, 1 and 2
@@ -435,6 +547,9 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAND_ATTR void k_candidates_full(
 static void launch_candidates(int mode, const Params& P, const Ws& W, double kap, hipStream_t s)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
+    // the per-block bounds of the walk's reach follow the block maxima of
+    // every level below the finest
+    const double* bound = W.reach + reach_level_offset(P.lcap);
     // the records hold the squared short reach; the full pass scales it by
     // at least (kap / lambda)^2 (the slack scales with it, which only widens)
     const double lam = fmin(kFusedReach, P.kappa);
@@ -445,13 +560,13 @@ static void launch_candidates(int mode, const Params& P, const Ws& W, double kap
         constexpr int kPer = decltype(per)::value;
         if (mode == 1)
             k_candidates_full<kPer, 1><<<grid_xcd(nb), kBlock, 0, s>>>(
-                P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand, kap, sc, W.flag);
+                P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand, kap, sc, W.flag, W.keys0, bound);
         else if (mode == 2)
             k_candidates_full<kPer, 2><<<grid_xcd(nb), kBlock, 0, s>>>(
-                P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand, kap, sc, W.flag);
+                P, W.dom, W.cells, W.p4, W.pf, W.nk, W.cand, kap, sc, W.flag, W.keys0, bound);
         else
             k_candidates<kPer><<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.cells, W.p4, W.pf,
-                                                               W.nk, W.cand, kap, sc, W.flag);
+                                                               W.nk, W.cand, kap, sc, W.flag, W.keys0, bound);
     });
 }
 
@@ -728,6 +843,18 @@ hipError_t launch_fused_h_lists(const Params& P, const Layout& L, const Ws& W, s
     k_hmax_begin<<<1, 1, 0, s>>>(W.dom);
     int64_t cb = (L.ncells_cap + kBlock - 1) / kBlock;
     k_cells_hmax<<<cb, kBlock, 0, s>>>(P, W.dom, W.cells, p->h, L.ncells_cap);
+    // the walk's reach bounds: the block level, the block maxima of the levels
+    // from the finest down to it, then each block's bound
+    k_reach_level<<<1, 1, 0, s>>>(P, W.dom);
+    for (int l = L.lcap - 1; l >= 0; --l) {
+        const int64_t nl = int64_t(1) << (3 * l);
+        k_reach_up<<<(nl + kBlock - 1) / kBlock, kBlock, 0, s>>>(W.dom, W.cells, W.reach, l);
+    }
+    {
+        const int64_t nl = L.lcap > 0 ? int64_t(1) << (3 * (L.lcap - 1)) : 1;
+        k_reach_bound<<<(nl + kBlock - 1) / kBlock, kBlock, 0, s>>>(
+            P, W.dom, W.cells, W.reach, W.reach + reach_level_offset(L.lcap));
+    }
     mk.at(0, s);
     // short reach first; the full-reach pair runs only if an h left it (the
     // kernels read the device flag and return at once when it is clear)
