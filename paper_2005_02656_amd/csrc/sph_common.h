@@ -620,6 +620,11 @@ SPH_DEV void finish_density(const Params& P, Domain* dom, const DensOut& O, int6
 #ifndef SPH_MOM_U_BATCH
 #define SPH_MOM_U_BATCH 2
 #endif
+// the mixed-precision momentum pass over 64-byte records, staged the same way
+// (20 KB of LDS per batch and workgroup)
+#ifndef SPH_MOM_M_U_BATCH
+#define SPH_MOM_M_U_BATCH 2
+#endif
 
 // neighbour loops load this many neighbours' records before computing on them
 // (independent gathers in flight per wavefront)

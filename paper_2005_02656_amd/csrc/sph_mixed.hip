@@ -12,8 +12,9 @@
 // 3x3 inversion, the integrator and the global sums stay in FP64.
 //
 // Gathered bytes per neighbour: 16 (position) + 4 (mass or volume) in the
-// density and IAD passes, one 80-byte record in the momentum pass, or 16 + 48
-// bytes with equal masses and sound speeds (FP64: 32 + 8, 32, and 144 or 112).
+// density and IAD passes, one 80-byte record in the momentum pass, or one
+// 64-byte record, staged through LDS by the wavefront, with equal masses and
+// sound speeds (FP64: 32 + 8, 32, and 144 or 112).
 #include "sph_common.h"
 #include "sph_mixed_geom.h"
 
@@ -39,8 +40,10 @@ struct alignas(16) RecM {
 };
 
 // the same factors when every mass and sound speed is equal (m and c from
-// slot 0), without the position: three columns, read with the 16-byte PosM
+// slot 0): four columns, which the wavefront stages through LDS together
 struct alignas(16) RecMU {
+    float ox, oy, oz;
+    uint32_t cpack;
     float k11, k12, k13, k22, k23, k33;
     float q, ih;
     float vx, vy, vz;
@@ -267,6 +270,7 @@ __device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, const Pos
 __device__ __forceinline__ RecMU make_recmu(const RecM& f)
 {
     RecMU q;
+    q.ox = f.ox; q.oy = f.oy; q.oz = f.oz; q.cpack = f.cpack;
     q.k11 = f.k11; q.k12 = f.k12; q.k13 = f.k13; q.k22 = f.k22; q.k23 = f.k23; q.k33 = f.k33;
     q.q = f.q; q.ih = f.ih;
     q.vx = f.vx; q.vy = f.vy; q.vz = f.vz;
@@ -390,25 +394,17 @@ struct MomSelfM {
     const double *h, *c, *c11, *c12, *c13, *c22, *c23, *c33, *rho, *omega, *p, *m;
 };
 
-__device__ __forceinline__ PosM rec_pos(const RecM& r) { return PosM{r.ox, r.oy, r.oz, r.cpack}; }
+template <class Rec>
+__device__ __forceinline__ PosM rec_pos(const Rec& r) { return PosM{r.ox, r.oy, r.oz, r.cpack}; }
 
-// a neighbour's record and position: one 80-byte record, or with equal masses
-// and sound speeds the 48-byte record and the 16-byte position record
+// a neighbour's record (its position in the first column): 80 bytes, or 64
+// with equal masses and sound speeds
 struct NbrM {
     const RecM* rec;
     const RecMU* recu;
-    const PosM* pm;
 };
-SPH_DEV void load_nbr(const NbrM& N, int32_t b, RecM& r, PosM& q)
-{
-    r = N.rec[b];
-    q = rec_pos(r);
-}
-SPH_DEV void load_nbr(const NbrM& N, int32_t b, RecMU& r, PosM& q)
-{
-    r = N.recu[b];
-    q = N.pm[b];
-}
+SPH_DEV const RecM* nbr_recs(const NbrM& N, const RecM&) { return N.rec; }
+SPH_DEV const RecMU* nbr_recs(const NbrM& N, const RecMU&) { return N.recu; }
 SPH_DEV float nbr_m(const RecM& r, float) { return r.m; }
 SPH_DEV float nbr_c(const RecM& r, float) { return r.c; }
 SPH_DEV float nbr_m(const RecMU&, float m0) { return m0; }
@@ -421,14 +417,18 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
                                                   const int32_t* __restrict__ list,
                                                   const NbrM& N, const MomSelfM& T,
                                                   const double* __restrict__ u,
-                                                  const MomOutM& O, int64_t a)
+                                                  const MomOutM& O, int64_t a_lane)
 {
+    // lanes past the end shadow the last slot with an empty list (every lane
+    // of a wavefront takes part in the staged gathers)
+    const bool live = a_lane < P.n;
+    const int64_t a = live ? a_lane : P.n - 1;
     double dtc = INFINITY;
-    if (a < P.n) {
+    {
         const CellGeom g = cell_geom(P, *dom);
-        Rec ra;
-        PosM pa;
-        load_nbr(N, (int32_t)a, ra, pa);
+        const Rec* __restrict__ recs = nbr_recs(N, Rec{});
+        const Rec ra = recs[a];
+        const PosM pa = rec_pos(ra);
         const float m0 = (float)T.m[0], c0 = (float)T.c[0];   // the uniform record's m, c
         const double ha = T.h[a];
         const float tsa = (float)(kPiHalfSq / (ha * ha));
@@ -441,11 +441,12 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
         const float ca11 = (float)T.c11[a], ca12 = (float)T.c12[a], ca13 = (float)T.c13[a];
         const float ca22 = (float)T.c22[a], ca23 = (float)T.c23[a], ca33 = (float)T.c33[a];
         const int ng = P.ng_max;
-        const int cg = min(nc[a], ng);
-        const int co = min(ns[a] - nc[a], ng);
+        const int cg = live ? min(nc[a], ng) : 0;
+        const int co = live ? min(ns[a] - nc[a], ng) : 0;
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
-        constexpr int kB = SPH_MOM_BATCH;
+        constexpr bool kStaged = sizeof(Rec) == sizeof(RecMU);
+        constexpr int kB = kStaged ? SPH_MOM_M_U_BATCH : SPH_MOM_BATCH;
         // list entries of the batch starting at k0 (-1 past the end); the next
         // batch's are fetched while this batch computes
         auto entries = [&](int k0, int32_t (&e)[kB]) {
@@ -456,26 +457,10 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
                 e[u] = (k < total) ? list[lpos(a, j, ng)] : -1;
             }
         };
-        int32_t nx[kB];
-        entries(0, nx);
-        for (int k0 = 0; k0 < total; k0 += kB) {
-            bool okv[kB];
-            Rec rbv[kB];
-            PosM qv[kB];
-#pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                okv[u] = (uint32_t)nx[u] < (uint32_t)P.n;
-                load_nbr(N, okv[u] ? nx[u] : (int32_t)a, rbv[u], qv[u]);
-            }
-            entries(k0 + kB, nx);
-#pragma unroll
-            for (int u = 0; u < kB; ++u) {
+        auto pair = [&](bool gather, const Rec& rb) {
 #pragma clang fp contract(fast)
-            if (!okv[u]) continue;
-            const bool gather = k0 + u < cg;
-            const Rec& rb = rbv[u];
             float dx, dy, dz;
-            const float r2 = disp_m(g, pa, qv[u], dx, dy, dz);
+            const float r2 = disp_m(g, pa, rec_pos(rb), dx, dy, dz);
             float Wa = 0.0f;
             if (gather) Wa = w0a * kern_S_f_t<kTab>(P, r2 * tsa);
             // support of W(h_b): v_b < 2, i.e. t_b < pi^2
@@ -507,26 +492,84 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
             const float vk = vx * Kx + vy * Ky + vz * Kz;
             e1 += (double)(mb * va);
             e2 += (double)(hPi * (mb * ira * va + Wb * vk));
+        };
+        int32_t nx[kB];
+        entries(0, nx);
+        if constexpr (kStaged) {
+            // Staged gathers (the 64-byte records): in load i lane L takes
+            // column L mod 4 of record 16 i + L / 4, so that four lanes read
+            // one whole record and a load covers sixteen; the columns go to
+            // LDS at a stride of five columns per record (20 dwords: the
+            // lanes' reads of their own records then hit distinct banks)
+            constexpr int kCols = (int)(sizeof(Rec) / 16);
+            constexpr int kPad = kCols + 1;
+            static_assert(sizeof(Rec) % 16 == 0, "records of whole 16-byte columns");
+            __shared__ int4 stage[kBlock / 64][kB][64 * kPad];
+            const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+            int tmax = total;   // the wavefront runs to its longest list
+            for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
+            const int4* col = (const int4*)recs;
+            for (int k0 = 0; k0 < tmax; k0 += kB) {
+                bool ok[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+                    const int32_t src = ok[u] ? nx[u] : (int32_t)a;
+#pragma unroll
+                    for (int i = 0; i < kCols; ++i) {
+                        const int q = 64 * i + lane;
+                        const int r = q / kCols, c = q % kCols;
+                        const int32_t b = __shfl(src, r, 64);
+                        stage[wv][u][r * kPad + c] = col[(int64_t)b * kCols + c];
+                    }
+                }
+                entries(k0 + kB, nx);
+                // LDS operations of one wavefront complete in order; the fences
+                // keep the compiler from moving the reads above the writes or
+                // the next batch's writes above this batch's reads
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const Rec rb = *(const Rec*)&stage[wv][u][lane * kPad];
+                    if (ok[u]) pair(k0 + u < cg, rb);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+        } else {
+            for (int k0 = 0; k0 < total; k0 += kB) {
+                bool okv[kB];
+                Rec rbv[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    okv[u] = (uint32_t)nx[u] < (uint32_t)P.n;
+                    rbv[u] = recs[okv[u] ? nx[u] : (int32_t)a];
+                }
+                entries(k0 + kB, nx);
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    if (okv[u]) pair(k0 + u < cg, rbv[u]);
             }
         }
-        // the energy rate is assembled in FP64
-        const double du = (double)pa_ * e1 + 0.5 * e2;
-        O.ax[a] = axs;
-        O.ay[a] = ays;
-        O.az[a] = azs;
-        O.du[a] = du;
-        if (!isfinite(axs) || !isfinite(ays) || !isfinite(azs) || !isfinite(du))
-            set_err(dom, SPH_ERRBIT_NONFINITE);
-        const double cA = T.c[a];
-        dtc = P.courant * (ha / cA);
-        if (P.acc_dt > 0.0) {
-            double am = sqrt((axs * axs + ays * ays) + azs * azs);
-            double qa = P.acc_dt * sqrt(ha / am);
-            if (qa < dtc) dtc = qa;
-        }
-        if (P.energy_dt > 0.0) {
-            double qu = P.energy_dt * (fabs(u[a]) / fabs(du));
-            if (qu < dtc) dtc = qu;
+        if (live) {
+            // the energy rate is assembled in FP64
+            const double du = (double)pa_ * e1 + 0.5 * e2;
+            O.ax[a] = axs;
+            O.ay[a] = ays;
+            O.az[a] = azs;
+            O.du[a] = du;
+            if (!isfinite(axs) || !isfinite(ays) || !isfinite(azs) || !isfinite(du))
+                set_err(dom, SPH_ERRBIT_NONFINITE);
+            const double cA = T.c[a];
+            dtc = P.courant * (ha / cA);
+            if (P.acc_dt > 0.0) {
+                double am = sqrt((axs * axs + ays * ays) + azs * azs);
+                double qa = P.acc_dt * sqrt(ha / am);
+                if (qa < dtc) dtc = qa;
+            }
+            if (P.energy_dt > 0.0) {
+                double qu = P.energy_dt * (fabs(u[a]) / fabs(du));
+                if (qu < dtc) dtc = qu;
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, o, 64));
@@ -564,7 +607,7 @@ RecSrcM recm_src(const sph_particles* p)
 static_assert(sizeof(PosM) == 16, "PosM layout");
 static_assert(sizeof(RecM) == 80, "RecM layout");
 static_assert(sizeof(RecM) <= sizeof(MomRec), "RecM records alias the MomRec area");
-static_assert(sizeof(RecMU) == 48, "RecMU layout: an odd number of 16-byte columns");
+static_assert(sizeof(RecMU) == 64, "RecMU layout: four 16-byte columns");
 size_t mixed_posm_bytes() { return sizeof(PosM); }
 size_t mixed_rec_bytes() { return sizeof(RecM); }
 
@@ -621,7 +664,7 @@ hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const 
     MomOutM O{p->ax, p->ay, p->az, p->du};
     MomSelfM T{p->h, p->c, p->c11, p->c12, p->c13, p->c22, p->c23, p->c33, p->rho, p->omega, p->p,
                p->m};
-    NbrM N{(const RecM*)W.recm, (const RecMU*)W.recm, pm};
+    NbrM N{(const RecM*)W.recm, (const RecMU*)W.recm};
     k_dtmin_begin_m<<<1, 1, 0, s>>>(W.dom);
     with_table(P, [&](auto tab) {
         k_momentum_energy_m<decltype(tab)::value><<<grid_xcd(nb), kBlock, 0, s>>>(

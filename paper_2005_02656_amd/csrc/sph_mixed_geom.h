@@ -4,17 +4,18 @@
 // FP32 offset from that cell's origin, so the displacement b - a along one
 // axis is (cell difference) x (cell edge) + (offset difference), formed in
 // FP32 from small numbers.  On a periodic axis of nax cells (length
-// L = nax x edge) the minimum image is taken on the cell difference.  The
-// half-open image interval (-L/2, L/2] of the FP64 path decides the tie at a
-// cell difference of exactly nax/2: there the two images are L/2 + off and
+// L = nax x edge) the minimum image is taken on the cell difference.  At a
+// cell difference of exactly nax/2 the two images are L/2 + off and
 // -L/2 + off apart, and the nearer one depends on the sign of the offset
-// difference, not on the sign of the cell difference.
+// difference, not on the sign of the cell difference.  (With off = 0 both are
+// L/2 away; no such pair is within reach, since 4h < L.)
 //
 // Host and device: the kernels use it, and a host check compares it with the
 // FP64 minimum image.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace sph {
 
@@ -24,12 +25,12 @@ __host__ __device__ inline float axis_disp(int ca, int cb, float oa, float ob, f
     int dc = cb - ca;
     const float off = ob - oa;
     if (per) {
-        const int half = nax / 2;
-        if (dc > half) dc -= nax;
-        else if (dc < -half) dc += nax;
-        // |dc| = nax/2 (nax is even: a power of two): keep the image nearer a
-        if (dc == half && off > 0.0f) dc -= nax;
-        else if (dc == -half && off < 0.0f) dc += nax;
+        // nax is a power of two: dc mod nax, represented in [-nax/2, nax/2)
+        // when off >= 0 and in (-nax/2, nax/2] when off < 0, so that at
+        // |dc| = nax/2 the image taken is the one of sign opposite to off's
+        const int s = (int)(__builtin_bit_cast(uint32_t, off) >> 31);
+        const int half = nax >> 1;
+        dc = ((dc + half - s) & (nax - 1)) - half + s;
     }
     return (float)dc * ce + off;
 }
