@@ -464,3 +464,69 @@ def test_fused_step_periodic_patterns(per, uniform):
     for f in ("ax", "ay", "az"):
         assert rel_err(r.by_id(f), me[f], me["scale_a"]) < TOL, f
     assert rel_err(r.by_id("du"), me["du"], me["scale_du"]) < TOL
+
+
+def _two_density(seed=21):
+    """Periodic unit box holding a lattice of spacing 1/24 for x < 3/4 and one
+    of spacing 1/16 beyond, each point moved by up to 5% of its spacing per
+    axis; h = 1.44 local spacings, so h jumps by 1.5 across the two faces
+    x = 0 and x = 3/4.  The walk bounds h_b per block of the Morton hierarchy:
+    here the blocks are a quarter of the box (the finest level whose edge
+    exceeds 2 kappa h_max = 0.225), and those of 1/4 <= x < 1/2, whose 26
+    neighbours are all dense, bound h_b by the dense h alone."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos, h = [], []
+    for x0, x1, dx in ((0.0, 0.75, 1.0 / 24), (0.75, 1.0, 1.0 / 16)):
+        gx = np.arange(x0 + dx / 2, x1, dx)
+        g = np.arange(dx / 2, 1.0, dx)
+        X, Y, Z = np.meshgrid(gx, g, g, indexing="ij")
+        P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+        pos.append(P + rng.uniform(-0.05, 0.05, P.shape) * dx)
+        h.append(np.full(len(P), inputs.H_GUESS_SPACINGS * dx))
+    P = np.concatenate(pos)
+    n = len(P)
+    v = rng.normal(0.0, 0.1, size=(n, 3))
+    arr = dict(x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(), vx=v[:, 0].copy(),
+               vy=v[:, 1].copy(), vz=v[:, 2].copy(), m=np.full(n, 1.0 / n),
+               u=np.full(n, 1.0), h=np.concatenate(h), id=np.arange(n, dtype=np.int64))
+    return inputs.Workload(f"two_density{n}", arr, inputs.base_params())
+
+
+def test_fused_step_two_density():
+    """Lists built with the walk's reach bounded per block: where h changes
+    across the box every candidate count still lies between the exact count of
+    b != a with r_ab < 2 lam max(h0_a, h0_b) and that count at a reach larger
+    by 1e-3, and one fused step gives the oracle's h, exact lists, density and
+    rates."""
+    w = _two_density()
+    cfg, ocfg = configs(w, ng_max=NG)
+    a = w.arrays
+    r = Run(w, cfg)
+    sph.step(cfg, r.parts, r.g, r.ws)
+    assert r.status() == (0, 0)
+    nk_v, cap = sph.candidates_view(cfg, r.ws)
+    nk = np.empty(w.n, np.int64)
+    nk[r.ids()] = nk_v.cpu().numpy()
+    assert nk.max() <= cap
+    lams = sorted({min(sph.SHORT_REACH, cfg.h_ratio_max), cfg.h_ratio_max})
+    fs = [2 * l for l in lams] + [2 * l * (1 + 1e-3) for l in lams]
+    cnt = _reach_counts(w, a["h"], fs)
+    ok = np.zeros(w.n, bool)
+    for l in lams:
+        ok |= (cnt[2 * l] <= nk) & (nk <= cnt[2 * l * (1 + 1e-3)])
+    assert np.all(ok)
+    h_o = oracle.update_h(ocfg, a["x"], a["y"], a["z"], a["h"])
+    assert rel_err(r.by_id("h"), h_o) < TOL
+    P, nc, ns = r.neighbor_pairs()
+    nc_o, ns_o, lists, gath = oracle.neighbors(ocfg, a["x"], a["y"], a["z"], h_o)
+    assert np.array_equal(nc, nc_o) and np.array_equal(ns, ns_o)
+    assert np.array_equal(P, oracle_pairs(lists, gath))
+    rho_o, om_o, p_o, c_o = oracle.density(ocfg, a["x"], a["y"], a["z"], h_o, a["m"], a["u"])
+    assert rel_err(r.by_id("rho"), rho_o) < TOL
+    assert rel_err(r.by_id("omega"), om_o) < TOL
+    Cm, _ = oracle.iad(ocfg, a["x"], a["y"], a["z"], h_o, a["m"], rho_o)
+    me = oracle.momentum_energy(ocfg, a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"], h_o,
+                                a["m"], rho_o, om_o, p_o, c_o, Cm)
+    for f in ("ax", "ay", "az"):
+        assert rel_err(r.by_id(f), me[f], me["scale_a"]) < TOL, f
+    assert rel_err(r.by_id("du"), me["du"], me["scale_du"]) < TOL
