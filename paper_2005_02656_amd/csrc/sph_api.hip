@@ -55,7 +55,6 @@ Layout make_layout(int64_t n, int ng_max)
     L.cand_cap = candidate_capacity(ng_max);
     L.cand = take(sizeof(int32_t) * (size_t)L.cand_cap * padded);
     L.posm = take(mixed_posm_bytes() * n);
-    L.mf = take(sizeof(float) * n);
     L.mf2 = take(sizeof(float) * n);
     // kernel tables, sized for the largest kernel_table whatever the config
     L.tabS = take(sizeof(double2) * SPH_KERNEL_TABLE_MAX);
@@ -91,7 +90,6 @@ Ws carve(void* ws, const Layout& L)
     W.cand = (int32_t*)(b + L.cand);
     W.posm = (void*)(b + L.posm);
     W.recm = (void*)(b + L.rec);   // FP32 records use the first half of the FP64 record area
-    W.mf = (float*)(b + L.mf);
     W.mf2 = (float*)(b + L.mf2);
     W.p4 = (Pos4*)(b + L.p4);
     W.pf = (Pos4f*)(b + L.pf);

@@ -190,7 +190,7 @@ int candidate_capacity(int ng_max);
 // ---------------------------------------------------------------- workspace layout
 struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
-    size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm, mf, mf2;
+    size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm, mf2;
     size_t tabS, tabD, tabSf, tabDf;
     size_t flag, reach;
     size_t total;
@@ -215,9 +215,9 @@ struct Ws {
     double* vol;               // m/rho per particle (IAD pass)
     PosV* pv;                  // position and m/rho (IAD neighbour records)
     Pos4f* pf;                 // FP32 walk records of the fused candidate pass
-    void* posm;                // mixed precision: cell index + FP32 offsets (16 B)
+    void* posm;                // mixed precision: fixed-point position + FP32 mass (16 B)
     void* recm;                // mixed precision: FP32 momentum records (aliases rec)
-    float *mf, *mf2;           // mixed precision: FP32 mass and volume
+    float* mf2;                // mixed precision: FP32 volume
     double* tmp;               // permute scratch (aliases the list area)
     double2 *tabS, *tabD;      // kernel tables (kernel_table > 0), FP64 and FP32
     float2 *tabSf, *tabDf;
@@ -556,7 +556,7 @@ inline void with_table(const Params& P, F&& f)
 #define SPH_WAVES_NEWTON 4
 #endif
 #ifndef SPH_NEWTON_ATTR
-#define SPH_NEWTON_ATTR SPH_WAVES_CAP(SPH_WAVES_NEWTON)
+#define SPH_NEWTON_ATTR SPH_WAVES_EXACT(SPH_WAVES_NEWTON)
 #endif
 #ifndef SPH_FILTER_ATTR
 #define SPH_FILTER_ATTR SPH_WAVES_CAP(SPH_WAVES_SEARCH)

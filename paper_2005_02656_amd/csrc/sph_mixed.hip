@@ -3,18 +3,17 @@
 // The paper keeps FP64 throughout and names a mixed-precision approach as
 // future work (section 4.2).  This form evaluates every pair term of the
 // density, IAD and momentum/energy passes in FP32 and accumulates the
-// per-particle sums in FP64.  Positions are an FP64 cell origin (the cell of
-// the last build, recovered from a packed integer cell index) plus an FP32
-// offset, so a pair displacement is (cell difference x cell edge) + (offset
-// difference) in FP32 with the minimum image taken on cell indices
-// (axis_disp, sph_mixed_geom.h).  The
-// neighbour test that builds the lists, the Newton update of h, the EOS, the
-// 3x3 inversion, the integrator and the global sums stay in FP64.
+// per-particle sums in FP64.  Positions are 32-bit fixed-point coordinates
+// over the key domain, so a pair displacement is an exact integer difference
+// (modulo 2^32 on periodic axes: the minimum image) converted to FP32 and
+// scaled (fix_disp, sph_mixed_geom.h).  The neighbour test that builds the
+// lists, the Newton update of h, the EOS, the 3x3 inversion, the integrator
+// and the global sums stay in FP64.
 //
-// Gathered bytes per neighbour: 16 (position) + 4 (mass or volume) in the
-// density and IAD passes, one 80-byte record in the momentum pass, or one
-// 64-byte record, staged through LDS by the wavefront, with equal masses and
-// sound speeds (FP64: 32 + 8, 32, and 144 or 112).
+// Gathered bytes per neighbour: 16 (position and FP32 mass) in the density
+// pass, 16 + 4 (volume) in the IAD pass, one 80-byte record in the momentum
+// pass, or one 64-byte record, staged through LDS by the wavefront, with
+// equal masses and sound speeds (FP64: 32 + 8, 32, and 144 or 112).
 #include "sph_common.h"
 #include "sph_mixed_geom.h"
 
@@ -23,16 +22,16 @@ namespace {
 
 
 struct alignas(16) PosM {
-    float ox, oy, oz;     // offset from the cell origin
-    uint32_t cpack;       // cell coordinates, 10 bits per axis (x | y << 10 | z << 20)
+    uint32_t qx, qy, qz;  // fixed-point coordinates (fix_coord)
+    float m;              // mass
 };
 // a neighbour's momentum/energy record: its position as in PosM, then the
 // folded factors of the FP64 record (K = (m/rho) C, q = P/(Omega rho)).  Five
 // 16-byte columns: an odd stride puts the same field of the records that the
 // lanes of a wavefront load in different columns of their cache lines.
 struct alignas(16) RecM {
-    float ox, oy, oz;
-    uint32_t cpack;
+    uint32_t qx, qy, qz;
+    uint32_t pad;
     float k11, k12, k13, k22, k23, k33;
     float q, c, m, ih;
     float vx, vy, vz;
@@ -42,40 +41,37 @@ struct alignas(16) RecM {
 // the same factors when every mass and sound speed is equal (m and c from
 // slot 0): four columns, which the wavefront stages through LDS together
 struct alignas(16) RecMU {
-    float ox, oy, oz;
-    uint32_t cpack;
+    uint32_t qx, qy, qz;
+    uint32_t pad;
     float k11, k12, k13, k22, k23, k33;
     float q, ih;
     float vx, vy, vz;
     float spare;
 };
 
-struct CellGeom {
-    float ce[3];          // cell edges
-    int nax;
-    int periodic[3];
+// the FP32 unit length of each axis
+struct FixGeom {
+    float unit[3];
 };
 
-__device__ __forceinline__ CellGeom cell_geom(const Params& P, const Domain& D)
+__device__ __forceinline__ FixGeom fix_geom(const Params& P, const Domain& D)
 {
-    CellGeom g;
+    FixGeom g;
     for (int k = 0; k < 3; ++k) {
-        g.ce[k] = (float)D.cell[k];
-        g.periodic[k] = P.periodic[k];
+        double units;
+        fix_axis(D.lo[k], D.hi[k], P.periodic[k] != 0, units, g.unit[k]);
     }
-    g.nax = D.ncell_axis;
     return g;
 }
 
 // displacement b - a and its square, all FP32
-__device__ __forceinline__ float disp_m(const CellGeom& g, const PosM& a, const PosM& b, float& dx,
+__device__ __forceinline__ float disp_m(const FixGeom& g, const PosM& a, const PosM& b, float& dx,
                                         float& dy, float& dz)
 {
-    dx = axis_disp(a.cpack & 1023u, b.cpack & 1023u, a.ox, b.ox, g.ce[0], g.periodic[0], g.nax);
-    dy = axis_disp((a.cpack >> 10) & 1023u, (b.cpack >> 10) & 1023u, a.oy, b.oy, g.ce[1],
-                   g.periodic[1], g.nax);
-    dz = axis_disp(a.cpack >> 20, b.cpack >> 20, a.oz, b.oz, g.ce[2], g.periodic[2], g.nax);
-    return (dx * dx + dy * dy) + dz * dz;
+    dx = fix_disp(a.qx, b.qx, g.unit[0]);
+    dy = fix_disp(a.qy, b.qy, g.unit[1]);
+    dz = fix_disp(a.qz, b.qz, g.unit[2]);
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
 template <int K>
@@ -140,35 +136,33 @@ __device__ __forceinline__ void kern_terms_f(const Params& P, float t, float& S,
     else kern_terms_f_t<false>(P, t, S, vdS);
 }
 
-// positions as cell index + FP32 offset, and FP32 masses
+// fixed-point positions and FP32 masses
 __global__ __launch_bounds__(kBlock) void k_pack_posm(Params P, const Domain* __restrict__ dom,
                                                       const double* __restrict__ x,
                                                       const double* __restrict__ y,
                                                       const double* __restrict__ z,
                                                       const double* __restrict__ m,
-                                                      PosM* __restrict__ pm,
-                                                      float* __restrict__ mf)
+                                                      PosM* __restrict__ pm)
 {
     int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= P.n) return;
-    const Domain D = *dom;
-    const int sh = kKeyBits - D.level;
+    const Domain& D = *dom;
     const double pos[3] = {x[i], y[i], z[i]};
-    uint32_t c[3];
-    float o[3];
+    uint32_t q[3];
     for (int k = 0; k < 3; ++k) {
-        c[k] = quantize(pos[k], D.lo[k], D.scale[k]) >> sh;
-        o[k] = (float)((pos[k] - D.lo[k]) - (double)c[k] * D.cell[k]);
+        const bool per = P.periodic[k] != 0;
+        double units;
+        float unit;
+        fix_axis(D.lo[k], D.hi[k], per, units, unit);
+        q[k] = fix_coord(pos[k], D.lo[k], units, per);
     }
-    pm[i] = PosM{o[0], o[1], o[2], c[0] | (c[1] << 10) | (c[2] << 20)};
-    mf[i] = (float)m[i];
+    pm[i] = PosM{q[0], q[1], q[2], (float)m[i]};
 }
 
 __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_density_m(Params P, Domain* __restrict__ dom,
                                                       const int32_t* __restrict__ nc,
                                                       const int32_t* __restrict__ list,
                                                       const PosM* __restrict__ pm,
-                                                      const float* __restrict__ mf,
                                                       const double* __restrict__ h,
                                                       const double* __restrict__ m,
                                                       const double* __restrict__ u,
@@ -184,7 +178,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_densi
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
     if (a >= P.n) return;
-    const CellGeom g = cell_geom(P, *dom);
+    const FixGeom g = fix_geom(P, *dom);
     const PosM pa = pm[a];
     const double ha = h[a];
     const float tsc = (float)(kPiHalfSq / (ha * ha));
@@ -204,7 +198,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_densi
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             q[u] = pm[bb[u]];
-            mb[u] = mf[bb[u]];
+            mb[u] = q[u].m;
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -253,7 +247,7 @@ __device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, const Pos
                                           double c23, double c33)
 {
     RecM q;
-    q.ox = pa.ox; q.oy = pa.oy; q.oz = pa.oz; q.cpack = pa.cpack;
+    q.qx = pa.qx; q.qy = pa.qy; q.qz = pa.qz; q.pad = 0u;
     const double r = R.rho[a], m = R.m[a];
     const double v = m / r;
     q.k11 = (float)(v * c11); q.k12 = (float)(v * c12); q.k13 = (float)(v * c13);
@@ -270,7 +264,7 @@ __device__ __forceinline__ RecM make_recm(const RecSrcM& R, int64_t a, const Pos
 __device__ __forceinline__ RecMU make_recmu(const RecM& f)
 {
     RecMU q;
-    q.ox = f.ox; q.oy = f.oy; q.oz = f.oz; q.cpack = f.cpack;
+    q.qx = f.qx; q.qy = f.qy; q.qz = f.qz; q.pad = 0u;
     q.k11 = f.k11; q.k12 = f.k12; q.k13 = f.k13; q.k22 = f.k22; q.k23 = f.k23; q.k33 = f.k33;
     q.q = f.q; q.ih = f.ih;
     q.vx = f.vx; q.vy = f.vy; q.vz = f.vz;
@@ -305,7 +299,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
     if (a >= P.n) return;
-    const CellGeom g = cell_geom(P, *dom);
+    const FixGeom g = fix_geom(P, *dom);
     const PosM pa = pm[a];
     const double ha = h[a];
     const float tsc = (float)(kPiHalfSq / (ha * ha));
@@ -395,7 +389,7 @@ struct MomSelfM {
 };
 
 template <class Rec>
-__device__ __forceinline__ PosM rec_pos(const Rec& r) { return PosM{r.ox, r.oy, r.oz, r.cpack}; }
+__device__ __forceinline__ PosM rec_pos(const Rec& r) { return PosM{r.qx, r.qy, r.qz, 0.0f}; }
 
 // a neighbour's record (its position in the first column): 80 bytes, or 64
 // with equal masses and sound speeds
@@ -425,7 +419,7 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
     const int64_t a = live ? a_lane : P.n - 1;
     double dtc = INFINITY;
     {
-        const CellGeom g = cell_geom(P, *dom);
+        const FixGeom g = fix_geom(P, *dom);
         const Rec* __restrict__ recs = nbr_recs(N, Rec{});
         const Rec ra = recs[a];
         const PosM pa = rec_pos(ra);
@@ -478,7 +472,7 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
             const float xv = -(vx * dx + vy * dy + vz * dz);
             float hPi = 0.0f;   // Pi_ab / 2
             if (xv < 0.0f) {
-                const float w = xv * rsqrtf(r2);
+                const float w = xv * __builtin_amdgcn_rsqf(r2);
                 const float vsig = ca + nbr_c(rb, c0) - 3.0f * w;
                 hPi = -0.25f * al * vsig * w;
             }
@@ -614,7 +608,7 @@ size_t mixed_rec_bytes() { return sizeof(RecM); }
 hipError_t launch_pack_posm(const Params& P, const Ws& W, const sph_particles* p, hipStream_t s)
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
-    k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, (PosM*)W.posm, W.mf);
+    k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, (PosM*)W.posm);
     return hipGetLastError();
 }
 
@@ -623,12 +617,12 @@ hipError_t launch_density_mixed(const Params& P, const Layout& L, const Ws& W, s
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     PosM* pm = (PosM*)W.posm;
-    if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
+    if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm);
     // The weakly compressible EOS P = p_ref + c0^2 (rho - rho_ref) multiplies a
     // relative density error by c0^2 rho / |P| (about 340 on the rotating square
     // patch), so its density pair terms stay FP64; IAD and momentum stay mixed.
     if (P.eos == SPH_EOS_WEAKLY_COMPRESSIBLE) return launch_density(P, L, W, p, s, pack);
-    k_density_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, pm, W.mf, p->h, p->m,
+    k_density_m<<<grid_xcd(nb), kBlock, 0, s>>>(P, W.dom, W.nc, W.list, pm, p->h, p->m,
                                                 p->u, p->p_ref, p->rho_ref, p->rho, p->omega,
                                                 p->p, p->c);
     return hipGetLastError();
@@ -639,7 +633,7 @@ hipError_t launch_iad_mixed(const Params& P, const Layout& L, const Ws& W, sph_p
 {
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     PosM* pm = (PosM*)W.posm;
-    if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
+    if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm);
     if (write_rec) launch_uniform_check(P, W, p, s);
     k_volume_m<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.mf2);
     with_table(P, [&](auto tab) {
@@ -656,7 +650,7 @@ hipError_t launch_momentum_energy_mixed(const Params& P, const Layout& L, const 
     const int64_t nb = (P.n + kBlock - 1) / kBlock;
     PosM* pm = (PosM*)W.posm;
     if (pack) {
-        k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm, W.mf);
+        k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm);
         launch_uniform_check(P, W, p, s);
         k_pack_recm<<<nb, kBlock, 0, s>>>(P.n, W.dom, recm_src(p), pm, p->c11, p->c12, p->c13,
                                           p->c22, p->c23, p->c33, W.recm);

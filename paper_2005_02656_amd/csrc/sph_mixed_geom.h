@@ -1,38 +1,55 @@
 // sph_mixed_geom.h -- the FP32 pair displacement of the mixed-precision passes.
 //
-// A mixed-precision position is a cell index (of the last cell build) plus an
-// FP32 offset from that cell's origin, so the displacement b - a along one
-// axis is (cell difference) x (cell edge) + (offset difference), formed in
-// FP32 from small numbers.  On a periodic axis of nax cells (length
-// L = nax x edge) the minimum image is taken on the cell difference.  At a
-// cell difference of exactly nax/2 the two images are L/2 + off and
-// -L/2 + off apart, and the nearer one depends on the sign of the offset
-// difference, not on the sign of the cell difference.  (With off = 0 both are
-// L/2 away; no such pair is within reach, since 4h < L.)
+// A mixed-precision position is a 32-bit fixed-point coordinate per axis,
+// counted from the key domain's low corner.  On a periodic axis of length L
+// there are 2^32 units per L, so the difference of two coordinates taken
+// modulo 2^32 as a signed integer is the minimum image (at a difference of
+// exactly L/2 both images are equally near; no such pair is within reach,
+// since 4h < L).  On an open axis there are 2^31 - 1 units over the domain's
+// extent, so every difference fits a signed integer as it is.  The
+// displacement b - a along an axis is that integer, exact, converted to FP32
+// and multiplied by the FP32 unit length: three instructions, and relative
+// errors of a few 2^-24 plus two units.
 //
 // Host and device: the kernels use it, and a host check compares it with the
 // FP64 minimum image.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace sph {
 
-__host__ __device__ inline float axis_disp(int ca, int cb, float oa, float ob, float ce, bool per,
-                                           int nax)
+// units per length and the FP32 length of one unit for an axis [lo, hi)
+// (both 0 on an axis of zero extent, where every coordinate is 0)
+__host__ __device__ inline void fix_axis(double lo, double hi, bool per, double& units,
+                                         float& unit)
 {
-    int dc = cb - ca;
-    const float off = ob - oa;
-    if (per) {
-        // nax is a power of two: dc mod nax, represented in [-nax/2, nax/2)
-        // when off >= 0 and in (-nax/2, nax/2] when off < 0, so that at
-        // |dc| = nax/2 the image taken is the one of sign opposite to off's
-        const int s = (int)(__builtin_bit_cast(uint32_t, off) >> 31);
-        const int half = nax >> 1;
-        dc = ((dc + half - s) & (nax - 1)) - half + s;
+    const double ext = hi - lo;
+    if (!(ext > 0.0)) {
+        units = 0.0;
+        unit = 0.0f;
+        return;
     }
-    return (float)dc * ce + off;
+    const double span = per ? 4294967296.0 : 2147483647.0;
+    units = span / ext;
+    unit = (float)(ext / span);
+}
+
+// the coordinate of pos: on a periodic axis taken modulo 2^32 (any number of
+// periods away), on an open one clamped to [0, 2^31 - 1]
+__host__ __device__ inline uint32_t fix_coord(double pos, double lo, double units, bool per)
+{
+    const double t = floor((pos - lo) * units);
+    if (per) return (uint32_t)(uint64_t)(int64_t)t;
+    return (uint32_t)fmin(fmax(t, 0.0), 2147483647.0);
+}
+
+// displacement b - a along the axis
+__host__ __device__ inline float fix_disp(uint32_t qa, uint32_t qb, float unit)
+{
+    return (float)(int32_t)(qb - qa) * unit;
 }
 
 }  // namespace sph

@@ -1,13 +1,15 @@
-// Host check of the mixed-precision pair displacement (sph::axis_disp) against
-// the FP64 minimum image with the half-open interval (-L/2, L/2].
+// Host check of the mixed-precision pair displacement (sph::fix_coord,
+// sph::fix_disp) against the FP64 displacement: the minimum image with the
+// half-open interval (-L/2, L/2] on a periodic axis, the plain difference on
+// an open one.
 //
-// For each number of cells per axis given on the command line, particles are
-// drawn uniformly on a periodic axis of length L = nax x edge, split into a
-// cell index and an FP32 offset, and every pair displacement the FP32 form
-// gives is compared with the FP64 one.  Prints one line per nax:
-//   nax pairs wrong worst_relative_error
-// and exits with status 1 if any pair took the wrong image or erred by more
-// than the rounding bound.
+// For each axis case, particles are drawn uniformly (on a periodic axis up to
+// two periods outside the box on either side, as positions that left it
+// would be), quantised, and every pair displacement the FP32 form gives is
+// compared with the FP64 one.  Prints one line per case:
+//   case pairs wrong worst_error_over_bound
+// for the bound 4 x 2^-24 |d| + 3 units, and exits with status 1 if any pair
+// took the wrong image or erred by more than the bound.
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -25,41 +27,53 @@ static double uniform01()   // splitmix64
     return (double)(z >> 11) * 0x1p-53;
 }
 
-int main(int argc, char** argv)
+struct Case {
+    bool per;
+    double lo, ext;
+};
+
+int main()
 {
+    const Case cases[] = {
+        {true, 0.0, 1.0},   {true, -0.5, 1.0},  {true, 12.3, 0.37},
+        {true, -7.0, 1000.0}, {false, 0.0, 1.0}, {false, -3.25, 1e-3},
+        {false, 100.0, 1e4},
+    };
     int bad_total = 0;
-    for (int ai = 1; ai < argc; ++ai) {
-        const int nax = atoi(argv[ai]);
-        const double ce = 1.0 / nax;   // unit box
-        const double L = nax * ce;
+    for (int ci = 0; ci < (int)(sizeof(cases) / sizeof(cases[0])); ++ci) {
+        const Case& c = cases[ci];
+        double units;
+        float unit;
+        sph::fix_axis(c.lo, c.lo + c.ext, c.per, units, unit);
         const int np = 600;
         double x[np];
-        int c[np];
-        float o[np];
+        uint32_t q[np];
         for (int i = 0; i < np; ++i) {
-            x[i] = uniform01() * L;
-            int ci = (int)floor(x[i] / ce);
-            if (ci > nax - 1) ci = nax - 1;
-            c[i] = ci;
-            o[i] = (float)(x[i] - ci * ce);
+            const double u = c.per ? 5.0 * uniform01() - 2.0 : uniform01();
+            x[i] = c.lo + u * c.ext;
+            q[i] = sph::fix_coord(x[i], c.lo, units, c.per);
         }
+        const double L = c.ext;
         long pairs = 0, wrong = 0;
         double worst = 0.0;
         for (int a = 0; a < np; ++a)
             for (int b = 0; b < np; ++b) {
                 double d = x[b] - x[a];
-                if (d > 0.5 * L) d -= L;
-                else if (d <= -0.5 * L) d += L;
-                if (fabs(fabs(d) - 0.5 * L) < 1e-5 * L) continue;   // image tie: either is right
-                const float f = sph::axis_disp(c[a], c[b], o[a], o[b], (float)ce, true, nax);
+                if (c.per) {
+                    d -= L * floor(d / L);   // [0, L)
+                    if (d > 0.5 * L) d -= L;
+                    // image tie: either is right
+                    if (fabs(fabs(d) - 0.5 * L) < 1e-5 * L) continue;
+                }
+                const float f = sph::fix_disp(q[a], q[b], unit);
                 const double err = fabs((double)f - d);
-                const double bound = 8.0 * 0x1p-24 * (fabs(d) + ce);
+                const double u1 = 1.0 / units;
+                const double bound = 4.0 * 0x1p-24 * fabs(d) + 3.0 * u1;
                 ++pairs;
                 if (err > bound) ++wrong;
-                const double rel = err / (fabs(d) + ce);
-                if (rel > worst) worst = rel;
+                if (err / bound > worst) worst = err / bound;
             }
-        printf("%d %ld %ld %.3e\n", nax, pairs, wrong, worst);
+        printf("%d %ld %ld %.3e\n", ci, pairs, wrong, worst);
         bad_total += wrong > 0;
     }
     return bad_total ? 1 : 0;
