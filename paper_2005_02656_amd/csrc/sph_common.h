@@ -339,6 +339,26 @@ SPH_DEV double disp_p(const Params& P, double xa, double ya, double za, double x
     return r2;
 }
 
+// A record staged in LDS, read back as whole 16-byte columns.  Staged records
+// sit at strides (20 or 28 dwords) where 16-byte reads by the lanes of a
+// wavefront hit distinct banks but narrower ones conflict two to four ways;
+// read as a structure, the compiler may split the record into 8-byte or
+// dword pairs, so the columns are read as 4-dword vectors first.
+template <class Rec>
+SPH_DEV Rec lds_record(const int4* col)
+{
+    static_assert(sizeof(Rec) % 16 == 0, "records of whole 16-byte columns");
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    constexpr int kCols = (int)(sizeof(Rec) / 16);
+    const v4i* src = (const v4i*)col;
+    v4i cw[kCols];
+#pragma unroll
+    for (int i = 0; i < kCols; ++i) cw[i] = src[i];
+    Rec r;
+    __builtin_memcpy(&r, cw, sizeof(Rec));
+    return r;
+}
+
 // The two lanes of a pair (2q, 2q+1) swap a 32-bit value (quad permute 1 0 3 2).
 SPH_DEV int32_t pair_swap(int32_t v)
 {

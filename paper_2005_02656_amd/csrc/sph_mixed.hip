@@ -498,7 +498,8 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
             // banks).  Dword-wide reads at that stride conflict four ways:
             // a layout whose used fields let the compiler pair dwords across
             // column boundaries (7 ds_read2_b32 per record instead of
-            // 16-byte reads) made this pass 26.5 -> 30.9 ms at 64 M particles.
+            // 16-byte reads) made this pass 26.5 -> 30.9 ms at 64 M particles,
+            // hence lds_record.
             constexpr int kCols = (int)(sizeof(Rec) / 16);
             constexpr int kPad = kCols + 1;
             static_assert(sizeof(Rec) % 16 == 0, "records of whole 16-byte columns");
@@ -528,7 +529,7 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
-                    const Rec rb = *(const Rec*)&stage[wv][u][lane * kPad];
+                    const Rec rb = lds_record<Rec>(&stage[wv][u][lane * kPad]);
                     if (ok[u]) pair(k0 + u < cg, rb);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

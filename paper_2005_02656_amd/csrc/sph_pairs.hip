@@ -410,7 +410,7 @@ __device__ __forceinline__ void momentum_energy(const Params& P, Domain* __restr
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
                 for (int u = 0; u < kMomBatch; ++u) {
-                    const Rec rb = *(const Rec*)&stage[wv][u][lane * kCols];
+                    const Rec rb = lds_record<Rec>(&stage[wv][u][lane * kCols]);
                     if (ok[u]) pair(k0 + u < cg, rb);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
