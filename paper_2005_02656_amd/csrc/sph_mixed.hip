@@ -57,9 +57,10 @@ struct FixGeom {
 __device__ __forceinline__ FixGeom fix_geom(const Params& P, const Domain& D)
 {
     FixGeom g;
+    const double emax = fix_emax(D.lo, D.hi);
     for (int k = 0; k < 3; ++k) {
-        double units;
-        fix_axis(D.lo[k], D.hi[k], P.periodic[k] != 0, units, g.unit[k]);
+        double origin, units;
+        fix_axis(D.lo[k], D.hi[k], P.periodic[k] != 0, emax, origin, units, g.unit[k]);
     }
     return g;
 }
@@ -148,13 +149,14 @@ __global__ __launch_bounds__(kBlock) void k_pack_posm(Params P, const Domain* __
     if (i >= P.n) return;
     const Domain& D = *dom;
     const double pos[3] = {x[i], y[i], z[i]};
+    const double emax = fix_emax(D.lo, D.hi);
     uint32_t q[3];
     for (int k = 0; k < 3; ++k) {
         const bool per = P.periodic[k] != 0;
-        double units;
+        double origin, units;
         float unit;
-        fix_axis(D.lo[k], D.hi[k], per, units, unit);
-        q[k] = fix_coord(pos[k], D.lo[k], units, per);
+        fix_axis(D.lo[k], D.hi[k], per, emax, origin, units, unit);
+        q[k] = fix_coord(pos[k], origin, units, per);
     }
     pm[i] = PosM{q[0], q[1], q[2], (float)m[i]};
 }

@@ -4,8 +4,10 @@
 // an open one.
 //
 // For each axis case, particles are drawn uniformly (on a periodic axis up to
-// two periods outside the box on either side, as positions that left it
-// would be), quantised, and every pair displacement the FP32 form gives is
+// two periods outside the box on either side, on an open one up to one extent
+// outside the bounding box, as positions that left it would be; an axis of
+// zero extent spreads them over the domain's extent), quantised,
+// and every pair displacement the FP32 form gives is
 // compared with the FP64 one.  Prints one line per case:
 //   case pairs wrong worst_error_over_bound
 // for the bound 4 x 2^-24 |d| + 3 units, and exits with status 1 if any pair
@@ -30,28 +32,30 @@ static double uniform01()   // splitmix64
 struct Case {
     bool per;
     double lo, ext;
+    double emax;   // the domain's largest extent (an open axis of zero extent takes it)
 };
 
 int main()
 {
     const Case cases[] = {
-        {true, 0.0, 1.0},   {true, -0.5, 1.0},  {true, 12.3, 0.37},
-        {true, -7.0, 1000.0}, {false, 0.0, 1.0}, {false, -3.25, 1e-3},
-        {false, 100.0, 1e4},
+        {true, 0.0, 1.0, 1.0},      {true, -0.5, 1.0, 1.0},   {true, 12.3, 0.37, 0.37},
+        {true, -7.0, 1000.0, 1000.0}, {false, 0.0, 1.0, 1.0},  {false, -3.25, 1e-3, 1e-3},
+        {false, 100.0, 1e4, 1e4},   {false, 2.0, 0.0, 0.5},
     };
     int bad_total = 0;
     for (int ci = 0; ci < (int)(sizeof(cases) / sizeof(cases[0])); ++ci) {
         const Case& c = cases[ci];
-        double units;
+        double origin, units;
         float unit;
-        sph::fix_axis(c.lo, c.lo + c.ext, c.per, units, unit);
+        sph::fix_axis(c.lo, c.lo + c.ext, c.per, c.emax, origin, units, unit);
+        const double len = c.ext > 0.0 ? c.ext : c.emax;
         const int np = 600;
         double x[np];
         uint32_t q[np];
         for (int i = 0; i < np; ++i) {
-            const double u = c.per ? 5.0 * uniform01() - 2.0 : uniform01();
-            x[i] = c.lo + u * c.ext;
-            q[i] = sph::fix_coord(x[i], c.lo, units, c.per);
+            const double u = c.per ? 5.0 * uniform01() - 2.0 : 3.0 * uniform01() - 1.0;
+            x[i] = c.lo + u * len;
+            q[i] = sph::fix_coord(x[i], origin, units, c.per);
         }
         const double L = c.ext;
         long pairs = 0, wrong = 0;

@@ -3,7 +3,8 @@ fixed-point coordinates, their integer difference modulo 2^32 on periodic axes,
 converted and scaled) must pick the same periodic image as the FP64 half-open
 minimum image and stay within a few FP32 roundings plus three units, on
 periodic axes of several lengths and offsets (positions up to two periods
-outside the box) and open axes of several extents."""
+outside the box) and open axes of several extents (positions up to one extent
+outside the bounding box, including an axis of zero extent)."""
 import os
 import shutil
 import subprocess
@@ -25,7 +26,7 @@ def test_fixed_point_displacement(tmp_path):
                    check=True, capture_output=True)
     r = subprocess.run([exe], capture_output=True, text=True)
     rows = [list(map(float, ln.split())) for ln in r.stdout.split("\n") if ln.strip()]
-    assert len(rows) == 7, r.stdout + r.stderr
+    assert len(rows) == 8, r.stdout + r.stderr
     for case, pairs, wrong, worst in rows:
         assert pairs > 300000
         assert wrong == 0, f"case {case:g}: {wrong:g} pairs outside the bound"
