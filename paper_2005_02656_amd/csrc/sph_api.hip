@@ -55,7 +55,6 @@ Layout make_layout(int64_t n, int ng_max)
     L.cand_cap = candidate_capacity(ng_max);
     L.cand = take(sizeof(int32_t) * (size_t)L.cand_cap * padded);
     L.posm = take(mixed_posm_bytes() * n);
-    L.mf2 = take(sizeof(float) * n);
     // kernel tables, sized for the largest kernel_table whatever the config
     L.tabS = take(sizeof(double2) * SPH_KERNEL_TABLE_MAX);
     L.tabD = take(sizeof(double2) * SPH_KERNEL_TABLE_MAX);
@@ -90,7 +89,6 @@ Ws carve(void* ws, const Layout& L)
     W.cand = (int32_t*)(b + L.cand);
     W.posm = (void*)(b + L.posm);
     W.recm = (void*)(b + L.rec);   // FP32 records use the first half of the FP64 record area
-    W.mf2 = (float*)(b + L.mf2);
     W.p4 = (Pos4*)(b + L.p4);
     W.pf = (Pos4f*)(b + L.pf);
     W.rec = (MomRec*)(b + L.rec);

@@ -190,7 +190,7 @@ int candidate_capacity(int ng_max);
 // ---------------------------------------------------------------- workspace layout
 struct Layout {
     size_t domain, sums, keys0, keys1, idx0, idx1, hist, scanpart;
-    size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm, mf2;
+    size_t cells, nc, ns, nk, p4, pf, rec, vol, pv, list, cand, posm;
     size_t tabS, tabD, tabSf, tabDf;
     size_t flag, reach;
     size_t total;
@@ -215,9 +215,8 @@ struct Ws {
     double* vol;               // m/rho per particle (IAD pass)
     PosV* pv;                  // position and m/rho (IAD neighbour records)
     Pos4f* pf;                 // FP32 walk records of the fused candidate pass
-    void* posm;                // mixed precision: fixed-point position + FP32 mass (16 B)
+    void* posm;                // mixed precision: fixed-point position + FP32 mass or volume (16 B)
     void* recm;                // mixed precision: FP32 momentum records (aliases rec)
-    float* mf2;                // mixed precision: FP32 volume
     double* tmp;               // permute scratch (aliases the list area)
     double2 *tabS, *tabD;      // kernel tables (kernel_table > 0), FP64 and FP32
     float2 *tabSf, *tabDf;

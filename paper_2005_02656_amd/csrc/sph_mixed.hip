@@ -10,8 +10,8 @@
 // lists, the Newton update of h, the EOS, the 3x3 inversion, the integrator
 // and the global sums stay in FP64.
 //
-// Gathered bytes per neighbour: 16 (position and FP32 mass) in the density
-// pass, 16 + 4 (volume) in the IAD pass, one 80-byte record in the momentum
+// Gathered bytes per neighbour: 16 (position and FP32 mass, or volume) in the
+// density and IAD passes, one 80-byte record in the momentum
 // pass, or one 64-byte record, staged through LDS by the wavefront, with
 // equal masses and sound speeds (FP64: 32 + 8, 32, and 144 or 112).
 #include "sph_common.h"
@@ -23,7 +23,7 @@ namespace {
 
 struct alignas(16) PosM {
     uint32_t qx, qy, qz;  // fixed-point coordinates (fix_coord)
-    float m;              // mass
+    float w;              // the mass (packed), then the volume m/rho (IAD pass)
 };
 // a neighbour's momentum/energy record: its position as in PosM, then the
 // folded factors of the FP64 record (K = (m/rho) C, q = P/(Omega rho)).  Five
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_densi
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             q[u] = pm[bb[u]];
-            mb[u] = q[u].m;
+            mb[u] = q[u].w;
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -232,12 +232,15 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_densi
         set_err(dom, SPH_ERRBIT_NONFINITE);
 }
 
+// the volume m/rho in the position records' spare lane, once the densities
+// that read the masses there are done: the IAD pass gathers one record per
+// neighbour
 __global__ __launch_bounds__(kBlock) void k_volume_m(int64_t n, const double* __restrict__ m,
                                                      const double* __restrict__ rho,
-                                                     float* __restrict__ vol)
+                                                     PosM* __restrict__ pm)
 {
     int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (i < n) vol[i] = (float)(m[i] / rho[i]);
+    if (i < n) pm[i].w = (float)(m[i] / rho[i]);
 }
 
 struct RecSrcM {
@@ -289,7 +292,6 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
                                                   const int32_t* __restrict__ nc,
                                                   const int32_t* __restrict__ list,
                                                   const PosM* __restrict__ pm,
-                                                  const float* __restrict__ vol,
                                                   const double* __restrict__ h,
                                                   double* __restrict__ c11, double* __restrict__ c12,
                                                   double* __restrict__ c13, double* __restrict__ c22,
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_iad_m
             ok[u] = (uint32_t)nx[u] < (uint32_t)P.n;
             const int32_t b = ok[u] ? nx[u] : (int32_t)a;
             q[u] = pm[b];
-            vb[u] = vol[b];
+            vb[u] = q[u].w;
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -642,10 +644,10 @@ hipError_t launch_iad_mixed(const Params& P, const Layout& L, const Ws& W, sph_p
     PosM* pm = (PosM*)W.posm;
     if (pack) k_pack_posm<<<nb, kBlock, 0, s>>>(P, W.dom, p->x, p->y, p->z, p->m, pm);
     if (write_rec) launch_uniform_check(P, W, p, s);
-    k_volume_m<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, W.mf2);
+    k_volume_m<<<nb, kBlock, 0, s>>>(P.n, p->m, p->rho, pm);
     with_table(P, [&](auto tab) {
         k_iad_m<decltype(tab)::value><<<grid_xcd(nb), kBlock, 0, s>>>(
-            P, W.dom, W.nc, W.list, pm, W.mf2, p->h, p->c11, p->c12, p->c13, p->c22, p->c23,
+            P, W.dom, W.nc, W.list, pm, p->h, p->c11, p->c12, p->c13, p->c22, p->c23,
             p->c33, recm_src(p), write_rec ? W.recm : nullptr);
     });
     return hipGetLastError();
