@@ -285,7 +285,7 @@ sph_status sph_gravity(const sph_config* cfg, const sph_particles* p,
  * device (the stream must belong to it).
  * Limit: configurations whose sph_workspace_bytes exceeds
  * SPH_STATIC_SCRATCH_BYTES return SPH_E_WORKSPACE before anything is enqueued
- * (64 MiB: about 26,000 particles at ng_max = 160).
+ * (64 MiB: 25,536 particles at ng_max = 160).
  * err_out: device pointer to one uint32 that receives this call's device error
  * word (SPH_ERRBIT_* bits) when the stream reaches the end of the step, or
  * NULL.  Each call starts from a cleared word.
