@@ -408,6 +408,11 @@ SPH_DEV float nbr_c(const RecM& r, float) { return r.c; }
 SPH_DEV float nbr_m(const RecMU&, float m0) { return m0; }
 SPH_DEV float nbr_c(const RecMU&, float c0) { return c0; }
 
+// the LDS staging of the momentum pass: batches of SPH_MOM_M_U_BATCH records
+// per wavefront at a stride of kMixPad columns (both record layouts)
+constexpr int kMixPad = 5;
+constexpr int kMixStage = (kBlock / 64) * SPH_MOM_M_U_BATCH * 64 * kMixPad;
+
 template <class Rec, bool kTab>
 __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __restrict__ dom,
                                                   const int32_t* __restrict__ nc,
@@ -415,7 +420,8 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
                                                   const int32_t* __restrict__ list,
                                                   const NbrM& N, const MomSelfM& T,
                                                   const double* __restrict__ u,
-                                                  const MomOutM& O, int64_t a_lane)
+                                                  const MomOutM& O, int64_t a_lane,
+                                                  int4* __restrict__ stage)
 {
     // lanes past the end shadow the last slot with an empty list (every lane
     // of a wavefront takes part in the staged gathers)
@@ -443,8 +449,7 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
         const int co = live ? min(ns[a] - nc[a], ng) : 0;
         double axs = 0.0, ays = 0.0, azs = 0.0, e1 = 0.0, e2 = 0.0;
         const int total = cg + co;
-        constexpr bool kStaged = sizeof(Rec) == sizeof(RecMU);
-        constexpr int kB = kStaged ? SPH_MOM_M_U_BATCH : SPH_MOM_BATCH;
+        constexpr int kB = SPH_MOM_M_U_BATCH;
         // list entries of the batch starting at k0 (-1 past the end); the next
         // batch's are fetched while this batch computes
         auto entries = [&](int k0, int32_t (&e)[kB]) {
@@ -493,22 +498,23 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
         };
         int32_t nx[kB];
         entries(0, nx);
-        if constexpr (kStaged) {
-            // Staged gathers (the 64-byte records): in load i lane L takes
-            // column L mod 4 of record 16 i + L / 4, so that four lanes read
-            // one whole record and a load covers sixteen; the columns go to
-            // LDS at a stride of five columns per record (20 dwords: the
-            // lanes' 16-byte reads of their own records then hit distinct
-            // banks).  Dword-wide reads at that stride conflict four ways:
-            // a layout whose used fields let the compiler pair dwords across
-            // column boundaries (7 ds_read2_b32 per record instead of
-            // 16-byte reads) made this pass 26.5 -> 30.9 ms at 64 M particles,
-            // hence lds_record.
+        {
+            // Staged gathers: in load i lane L takes column (64 i + L) mod C of
+            // record (64 i + L) / C (C = 4 columns with equal masses and sound
+            // speeds, else 5), so that C lanes read one whole record and a
+            // load covers 64 / C; the columns go to LDS at a stride of five
+            // columns per record (20 dwords: the lanes' 16-byte reads of their
+            // own records then hit distinct banks).  Dword-wide reads at that
+            // stride conflict four ways: a layout whose used fields let the
+            // compiler pair dwords across column boundaries (7 ds_read2_b32
+            // per record instead of 16-byte reads) made this pass 26.5 ->
+            // 30.9 ms at 64 M particles, hence lds_record.  C3 (unequal sound
+            // speeds): 7.66 -> 7.40 ms against per-lane gathers.
             constexpr int kCols = (int)(sizeof(Rec) / 16);
-            constexpr int kPad = kCols + 1;
             static_assert(sizeof(Rec) % 16 == 0, "records of whole 16-byte columns");
-            __shared__ int4 stage[kBlock / 64][kB][64 * kPad];
+            static_assert(kCols <= kMixPad, "the staging stride holds a record");
             const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+            int4* const mine = stage + wv * (kB * 64 * kMixPad);
             int tmax = total;   // the wavefront runs to its longest list
             for (int o = 32; o > 0; o >>= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
             const int4* col = (const int4*)recs;
@@ -523,7 +529,7 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
                         const int q = 64 * i + lane;
                         const int r = q / kCols, c = q % kCols;
                         const int32_t b = __shfl(src, r, 64);
-                        stage[wv][u][r * kPad + c] = col[(int64_t)b * kCols + c];
+                        mine[(u * 64 + r) * kMixPad + c] = col[(int64_t)b * kCols + c];
                     }
                 }
                 entries(k0 + kB, nx);
@@ -533,24 +539,10 @@ __device__ __forceinline__ void momentum_energy_m(const Params& P, Domain* __res
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
-                    const Rec rb = lds_record<Rec>(&stage[wv][u][lane * kPad]);
+                    const Rec rb = lds_record<Rec>(&mine[(u * 64 + lane) * kMixPad]);
                     if (ok[u]) pair(k0 + u < cg, rb);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            }
-        } else {
-            for (int k0 = 0; k0 < total; k0 += kB) {
-                bool okv[kB];
-                Rec rbv[kB];
-#pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    okv[u] = (uint32_t)nx[u] < (uint32_t)P.n;
-                    rbv[u] = recs[okv[u] ? nx[u] : (int32_t)a];
-                }
-                entries(k0 + kB, nx);
-#pragma unroll
-                for (int u = 0; u < kB; ++u)
-                    if (okv[u]) pair(k0 + u < cg, rbv[u]);
             }
         }
         if (live) {
@@ -594,10 +586,12 @@ __global__ __launch_bounds__(kBlock) SPH_WAVES_CAP(SPH_WAVES_MIXED) void k_momen
     const int64_t lb = xcd_block(nb);
     if (lb < 0) return;
     const int64_t a = lb * kBlock + threadIdx.x;
+    // one staging buffer for both layouts (two would both be allocated)
+    __shared__ int4 stage[kMixStage];
     if (dom->nonuniform)
-        momentum_energy_m<RecM, kTab>(P, dom, nc, ns, list, N, T, u, O, a);
+        momentum_energy_m<RecM, kTab>(P, dom, nc, ns, list, N, T, u, O, a, stage);
     else
-        momentum_energy_m<RecMU, kTab>(P, dom, nc, ns, list, N, T, u, O, a);
+        momentum_energy_m<RecMU, kTab>(P, dom, nc, ns, list, N, T, u, O, a, stage);
 }
 
 RecSrcM recm_src(const sph_particles* p)
