@@ -4,8 +4,9 @@ sph_step calls leaves (the graph holds the same kernels with the same
 arguments): checked bit for bit after each replay, with the program's own
 eager work and synchronisations between replays, on a lattice (equal masses
 and sound speeds, short-reach search) and on random particles with variable h
-(unequal records, the full-reach refit).  The eager steps themselves are held
-to the oracle by the parity tests."""
+(unequal records, the full-reach refit), in FP64 and in mixed precision (whose
+position records switch their spare lane from mass to volume within a step).
+The eager steps themselves are held to the oracle by the parity tests."""
 import numpy as np
 import pytest
 import torch
@@ -35,10 +36,11 @@ def _same(a, b, where):
         assert np.array_equal(a[k], b[k]), (where, k)
 
 
+@pytest.mark.parametrize("precision", [sph.FP64, sph.MIXED])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_graph_replays_match_eager_steps(name):
+def test_graph_replays_match_eager_steps(name, precision):
     w = CASES[name]()
-    cfg, _ = configs(w, ng_max=400)
+    cfg, _ = configs(w, ng_max=400, precision=precision)
     eager = Run(w, cfg)
     sph.initialise(cfg, eager.parts, eager.ws, eager.g)
     ref = []
