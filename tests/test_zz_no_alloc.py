@@ -1,7 +1,8 @@
 """sph_step_static (the allocation-free step, scratch in the library's fixed
 device array) against sph_step with a caller workspace, through the C ABI: two
-calls in a row, the second with a smaller input, then a call whose lists
-overflow (error word set) and one after it (word cleared again)."""
+calls in a row, the second with a smaller input, in FP64 and in mixed
+precision, then a call whose lists overflow (error word set) and one after it
+(word cleared again)."""
 import numpy as np
 import pytest
 import torch
@@ -43,11 +44,12 @@ def _compare(cfg, a, b, gb, err):
     return st, bits
 
 
-def test_static_step_matches_workspace_step():
+@pytest.mark.parametrize("precision", [sph.FP64, sph.MIXED])
+def test_static_step_matches_workspace_step(precision):
     err = torch.full((1,), -1, dtype=torch.int32, device="cuda")
     # a 20^3 lattice (8,000 particles), then a smaller random set (3,001)
     for w in (inputs.c1_lattice(), inputs.random_periodic(3001, seed=4, h_lo=0.06, h_hi=0.09)):
-        cfg, a, b, gb = _pair(w, ng_max=400)
+        cfg, a, b, gb = _pair(w, ng_max=400, precision=precision)
         assert sph.lib().sph_workspace_bytes(__import__("ctypes").byref(cfg.c())) \
             <= sph.STATIC_SCRATCH_BYTES
         for _ in range(2):
